@@ -1,0 +1,195 @@
+/*
+ * dgtn.h -- C ABI of the MI355X (gfx950) discontinuous-Galerkin elasticity
+ * library for Brownian thermal noise in layered mirrors.
+ *
+ * Method: Vu et al., "High-accuracy numerical models of Brownian thermal noise
+ * in thin mirror coatings" (arXiv:2111.06893).  The library solves the
+ * auxiliary elastostatic problem of Sec. 2.1 (eqs. Newton, Hooke,
+ * elasticity_eqns) with the DG discretisation of Sec. 2.2 (eqs. dg_residuals,
+ * numflux, penalty, bc) and the Krylov solve of Sec. 2.3 (eq. matrix_eqn), and
+ * returns the elastic energy U (per layer) and the noise S_x of eqs.
+ * thermalnoise / wdiss.
+ *
+ * Conventions
+ *  - Every call returns a dgtn_status; 0 is success, negative is failure, and
+ *    dgtn_last_error() then returns a thread-local message.  No C++ exception
+ *    crosses this interface.
+ *  - Units are SI.  Device pointers are HIP device memory owned by the caller;
+ *    the library never frees caller memory.  Host pointers are plain host
+ *    memory.  Streams are the caller's; calls that return host values
+ *    synchronise the stream they were given.
+ *  - Field layout: u[e][c][k][j][i] (i fastest), c the Cartesian component,
+ *    (i, j, k) the LGL node indices along (xi, eta, zeta); zeta = -1 is the
+ *    element side nearer the loaded face z = 0.  Elements are numbered
+ *    e = iz * n_cols + col, iz counted from z = 0 downward; cylinder columns are
+ *    numbered block-major (centre square, wedges +x, +y, -x, -y), then by the
+ *    sub-square (s, t) of the block's 2^refine x 2^refine split, s fastest.
+ *  - The library allocates no device memory: the caller binds one device
+ *    workspace (dgtn_workspace_bytes / dgtn_bind) that holds the geometry,
+ *    face buffers, solver vectors and preconditioner data.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef DGTN_H
+#define DGTN_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque library context: problem, mesh and host-side geometry. */
+typedef struct dgtn_ctx dgtn_ctx;
+
+typedef enum {
+    DGTN_OK = 0,
+    DGTN_EINVAL = -1,   /* invalid argument or problem description         */
+    DGTN_EMESH = -2,    /* mesh construction failed (non-conforming, det<=0)*/
+    DGTN_EHIP = -3,     /* a HIP runtime call failed                       */
+    DGTN_ENOCONV = -4,  /* solver hit its iteration limit                  */
+    DGTN_ENOMEM = -5,   /* bound workspace too small                       */
+    DGTN_ENAN = -6      /* NaN/Inf met in the solver                       */
+} dgtn_status;
+
+enum { DGTN_DOMAIN_CYLINDER = 0, DGTN_DOMAIN_BOX = 1 };
+enum { DGTN_MAT_ISO = 0, DGTN_MAT_CUBIC = 1 };
+/* Boundary conditions (Sec. 2.2.4, eqs. bc, BCfixed, BCfree). */
+enum { DGTN_BC_DIRICHLET = 1, DGTN_BC_PRESSURE = 2, DGTN_BC_FREE = 3 };
+
+/* Constitutive relation of one material: isotropic (eq. constrel_iso, given
+ * by Young's modulus and Poisson ratio) or cubic with crystal axes along
+ * x, y, z (eq. constrel_cryst). */
+typedef struct {
+    int kind;                 /* DGTN_MAT_ISO or DGTN_MAT_CUBIC */
+    double youngs, poisson;   /* used when kind == DGTN_MAT_ISO */
+    double c11, c12, c44;     /* used when kind == DGTN_MAT_CUBIC */
+} dgtn_material;
+
+/* One z-layer (Sec. 2.2.1): thickness, number of elements across it, the
+ * geometric growth factor of consecutive element thicknesses (1 = uniform)
+ * and its material index. */
+typedef struct {
+    double thickness;
+    int n_elem;
+    double ratio;
+    int material;
+} dgtn_layer;
+
+/* Problem description (Sec. 2.1 and 2.2.1).  Cylinder: radius R, five blocks
+ * (centre square of half-width R/(2 sqrt 2) and four wedges blending its edges
+ * into the arc), each split 2^refine x 2^refine.  Box:
+ * [-Lx/2, Lx/2] x [-Ly/2, Ly/2] with nx x ny columns.  In z the layers are
+ * stacked from the loaded face z = 0 downward.  Load: Gaussian pressure of
+ * eq. laserbeam with total force F0, width r0, centred at (xc, yc), on faces
+ * tagged DGTN_BC_PRESSURE.  penalty is C of eq. penalty (100 in the paper). */
+typedef struct {
+    int domain;
+    double R;
+    int refine;
+    double Lx, Ly;
+    int nx, ny;
+    int p;                    /* polynomial degree, N = p + 1 LGL points, 1..7 */
+    int n_layers;
+    const dgtn_layer* layers;
+    int n_materials;
+    const dgtn_material* materials;
+    double F0, r0, xc, yc;
+    int bc_top, bc_bottom, bc_side;
+    double penalty;
+} dgtn_problem;
+
+typedef struct {
+    int n_elem, N, n_cols, n_zelem, n_layers;
+    long long n_dof;          /* 3 * n_elem * N^3 */
+    double y_ref;             /* modulus scale of the internal arithmetic (Pa) */
+} dgtn_info;
+
+/* Krylov solve (Sec. 2.3): restarted flexible GMRES in FP64 on A u = b,
+ * preconditioned by a multigrid V-cycle whose levels run in
+ * precond_precision (64 or 32 bit); every restart recomputes the FP64 true
+ * residual (iterative refinement when the preconditioner is FP32).
+ * mg_levels = 1 uses the smoother alone. */
+typedef struct {
+    int precond_precision;    /* 64 or 32                                      */
+    int restart;              /* FGMRES restart length m (1..200)              */
+    int max_iter;             /* total iteration cap                           */
+    double rtol;              /* stop at ||b - A u|| <= rtol ||b||             */
+    int mg_levels;            /* levels of the V-cycle (1 = smoother only)      */
+    int smooth_steps;         /* pre- and post-smoothing sweeps per level       */
+    double smooth_damping;    /* damping of the additive Schwarz smoother      */
+} dgtn_solve_opts;
+
+typedef struct {
+    int iters;
+    int restarts;
+    double rel_res;           /* final true relative residual (FP64)          */
+    double t_solve_s;         /* wall time of the solve                         */
+} dgtn_solve_stats;
+
+/* Builds the mesh and the host-side geometry of the problem (Sec. 2.2.1:
+ * isoparametric element maps, Jacobians, normals, surface Jacobians, widths h
+ * and penalties of eq. penalty).  Validates: p in 1..7, positive thicknesses,
+ * positive-definite materials (isotropic: Y > 0, -1 < nu < 1/2; cubic:
+ * c44 > 0, c11 > |c12|, c11 + 2 c12 > 0), conforming faces, det J > 0.
+ * On success *ctx owns host memory only. */
+dgtn_status dgtn_create(const dgtn_problem* prob, dgtn_ctx** ctx);
+
+dgtn_status dgtn_get_info(const dgtn_ctx* ctx, dgtn_info* info);
+
+/* Bytes of device workspace needed for the apply/rhs/energy calls and, if
+ * opts is non-NULL, for dgtn_solve with those options. */
+dgtn_status dgtn_workspace_bytes(const dgtn_ctx* ctx, const dgtn_solve_opts* opts,
+                                 size_t* bytes);
+
+/* Binds a device workspace of `bytes` bytes (256-byte aligned) and uploads
+ * the geometry into it on `stream`.  opts as in dgtn_workspace_bytes.  The
+ * workspace must stay allocated until dgtn_destroy or the next dgtn_bind. */
+dgtn_status dgtn_bind(dgtn_ctx* ctx, void* workspace, size_t bytes,
+                      const dgtn_solve_opts* opts, hipStream_t stream);
+
+/* Au = A u, the matrix-free DG operator of eq. dg_residuals (weak form, flux
+ * of eq. numflux with averaged moduli, penalty of eq. penalty, homogeneous
+ * boundary data of eq. bc), in SI units.  precision 64: u, Au are double;
+ * precision 32: float.  u and Au are device arrays of n_dof values in the
+ * field layout and must not alias. */
+dgtn_status dgtn_apply(dgtn_ctx* ctx, int precision, const void* u, void* Au,
+                       hipStream_t stream);
+
+/* b = load vector of the Gaussian pressure (eq. laserbeam, scaled by F0) on
+ * the DGTN_BC_PRESSURE faces, entering through the Neumann flux of eq. bc
+ * (device, double, n_dof). */
+dgtn_status dgtn_rhs(dgtn_ctx* ctx, double* b, hipStream_t stream);
+
+/* Solves A u = b; u holds the initial guess on entry and the solution on
+ * exit (device, double).  Returns DGTN_ENOCONV if max_iter is reached
+ * (u then holds the last iterate), DGTN_ENAN on a NaN/Inf. */
+dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* b,
+                       double* u, dgtn_solve_stats* stats, hipStream_t stream);
+
+/* Elastic energy per layer, U_k = 1/2 sum over the elements of layer k of
+ * int S_ij Y^ijkl S_kl dV with the unlifted strain S = D_(i u_j) and LGL
+ * quadrature (Sec. 2.1).  u: device double; U_layers: host, n_layers values.
+ * Synchronises the stream. */
+dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers,
+                        hipStream_t stream);
+
+/* Thermal-noise power spectral density from the layer energies:
+ * S_x = 4 kB T sum_k phi_k U_k / (pi f F0^2), the reading of eqs.
+ * thermalnoise / wdiss in which the dissipated power is 2 pi f U phi.  Pure
+ * host function. */
+dgtn_status dgtn_noise_psd(const double* U_layers, const double* phi, int n_layers,
+                           double T, double f, double F0, double* S_x);
+
+/* Node coordinates (host, double, [E][3][N^3]) of the library's mesh. */
+dgtn_status dgtn_node_coords(const dgtn_ctx* ctx, double* xyz);
+
+void dgtn_destroy(dgtn_ctx* ctx);
+
+const char* dgtn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGTN_H */

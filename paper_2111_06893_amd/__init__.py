@@ -1,0 +1,202 @@
+"""MI355X-native DG elasticity for Brownian coating thermal noise.
+
+Thin Python binding of the C ABI in include/dgtn.h (libdgtn.so, HIP for
+gfx950): argument marshalling only.  Every step of the operator, load, solve
+and energy runs in the library's kernels; PyTorch provides device memory and
+streams.  There is no CPU fallback: without the built library every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import DgtnError, check, load
+
+__all__ = ["Problem", "DgtnError", "noise_psd", "load", "problem_struct", "default_opts"]
+
+_BC = {"top", "bottom", "side"}
+
+
+def problem_struct(spec):
+    """ctypes problem description from a spec dict (kept alive by the result)."""
+    mats = (_lib.Material * len(spec["materials"]))()
+    for i, m in enumerate(spec["materials"]):
+        if m["kind"] == "iso":
+            mats[i] = _lib.Material(0, m["Y"], m["nu"], 0.0, 0.0, 0.0)
+        elif m["kind"] == "cubic":
+            mats[i] = _lib.Material(1, 0.0, 0.0, m["c11"], m["c12"], m["c44"])
+        else:
+            raise ValueError(m["kind"])
+    lays = (_lib.Layer * len(spec["layers"]))()
+    for i, l in enumerate(spec["layers"]):
+        lays[i] = _lib.Layer(l["thickness"], l["n_elem"], l["ratio"], l["material"])
+    ld = spec["load"]
+    bc = spec["bc"]
+    box = spec["domain"] == "box"
+    p = _lib.ProblemC(
+        domain=1 if box else 0, R=spec.get("R", 1.0), refine=0 if box else spec["refine"],
+        Lx=spec.get("Lx", 1.0), Ly=spec.get("Ly", 1.0), nx=spec.get("nx", 1), ny=spec.get("ny", 1),
+        p=spec["p"], n_layers=len(lays), layers=lays, n_materials=len(mats), materials=mats,
+        F0=ld["F0"], r0=ld["r0"], xc=ld["xc"], yc=ld["yc"],
+        bc_top=bc["top"], bc_bottom=bc["bottom"], bc_side=bc["side"], penalty=spec["penalty"])
+    return p, (mats, lays)
+
+
+def default_opts(precision=64, **kw):
+    o = dict(precond_precision=precision, restart=30, max_iter=20000, rtol=1e-11,
+             mg_levels=1, smooth_steps=1, smooth_damping=1.0)
+    o.update(kw)
+    return _lib.SolveOpts(**o)
+
+
+def noise_psd(U_layers, phi, T, f, F0):
+    """S_x = 4 kB T sum_k phi_k U_k / (pi f F0^2) (host function of the library)."""
+    lib = load()
+    U = np.ascontiguousarray(U_layers, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    if U.shape != ph.shape:
+        raise ValueError("U_layers and phi differ in length")
+    out = ctypes.c_double()
+    check(lib.dgtn_noise_psd(U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(U), T, f, F0,
+                             ctypes.byref(out)))
+    return out.value
+
+
+class Problem:
+    """One problem on the current HIP device.
+
+    spec: a problem description dict (see the workloads package).  The mesh
+    and host geometry are built at construction; the device workspace is
+    allocated as a torch uint8 tensor and bound when first needed.
+    """
+
+    def __init__(self, spec, opts=None, device=None):
+        self.lib = load()
+        self.spec = spec
+        self._struct, self._keep = problem_struct(spec)
+        ctx = ctypes.c_void_p()
+        check(self.lib.dgtn_create(ctypes.byref(self._struct), ctypes.byref(ctx)))
+        self.ctx = ctx
+        info = _lib.Info()
+        check(self.lib.dgtn_get_info(self.ctx, ctypes.byref(info)))
+        self.info = info
+        self.n_dof = info.n_dof
+        self.shape = (info.n_elem, 3, info.N, info.N, info.N)
+        self.n_layers = info.n_layers
+        self.y_ref = info.y_ref
+        self.ws = None
+        self.opts = opts
+        self.device = device
+
+    # --- host-only queries -------------------------------------------------
+    def workspace_bytes(self, opts=None):
+        n = ctypes.c_size_t()
+        check(self.lib.dgtn_workspace_bytes(self.ctx, ctypes.byref(opts) if opts is not None else None,
+                                            ctypes.byref(n)))
+        return n.value
+
+    def node_coords(self):
+        out = np.zeros(self.shape)
+        check(self.lib.dgtn_node_coords(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    # --- device -------------------------------------------------------------
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def bind(self, opts=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise DgtnError("no HIP device visible")
+        opts = opts if opts is not None else self.opts
+        nbytes = self.workspace_bytes(opts)
+        dev = self.device or torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        check(self.lib.dgtn_bind(self.ctx, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                 ctypes.byref(opts) if opts is not None else None, self._stream()))
+        self.opts = opts
+        return self
+
+    def _ensure(self, opts=None):
+        if self.ws is None or (opts is not None and self.opts is None):
+            self.bind(opts if opts is not None else self.opts)
+
+    def _check_field(self, t, dtype):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("expected a device tensor")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != self.n_dof:
+            raise ValueError(f"expected a contiguous {dtype} tensor of {self.n_dof} values")
+
+    def empty(self, dtype=None):
+        import torch
+        self._ensure()
+        return torch.empty(self.shape, dtype=dtype or torch.float64, device=self.ws.device)
+
+    def apply(self, u, out=None):
+        """A u (SI) in the precision of u (float64 or float32)."""
+        import torch
+        self._ensure()
+        prec = 64 if u.dtype == torch.float64 else 32
+        self._check_field(u, u.dtype)
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_field(out, u.dtype)
+        check(self.lib.dgtn_apply(self.ctx, prec, ctypes.c_void_p(u.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def rhs(self, out=None):
+        import torch
+        self._ensure()
+        if out is None:
+            out = self.empty(torch.float64)
+        self._check_field(out, torch.float64)
+        check(self.lib.dgtn_rhs(self.ctx, ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def energy(self, u):
+        """Per-layer elastic energies (numpy, J)."""
+        import torch
+        self._ensure()
+        self._check_field(u, torch.float64)
+        out = np.zeros(self.n_layers)
+        check(self.lib.dgtn_energy(self.ctx, ctypes.c_void_p(u.data_ptr()),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
+        return out
+
+    def solve(self, b=None, u0=None, opts=None):
+        """Solves A u = b (b defaults to the load vector); returns (u, stats)."""
+        import torch
+        opts = opts if opts is not None else (self.opts or default_opts())
+        if self.ws is None or self.opts is None or self.workspace_bytes(opts) > self.ws.numel():
+            self.bind(opts)
+        if b is None:
+            b = self.rhs()
+        self._check_field(b, torch.float64)
+        u = torch.zeros_like(b) if u0 is None else u0.clone()
+        stats = _lib.SolveStats()
+        st = self.lib.dgtn_solve(self.ctx, ctypes.byref(opts), ctypes.c_void_p(b.data_ptr()),
+                                 ctypes.c_void_p(u.data_ptr()), ctypes.byref(stats), self._stream())
+        check(st)
+        return u, stats
+
+    def noise(self, U_layers, phi, T, f):
+        return noise_psd(U_layers, phi, T, f, self.spec["load"]["F0"])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dgtn_destroy(self.ctx)
+            self.ctx = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

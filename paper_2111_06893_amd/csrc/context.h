@@ -1,0 +1,57 @@
+// The library context and the interfaces between its translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace dgtn {
+
+struct Layout {
+    size_t cursor = 0;
+    size_t take(size_t bytes);  // 256-byte aligned bump allocation
+};
+
+struct SolverState;  // defined in solver.hip
+
+}  // namespace dgtn
+
+struct dgtn_ctx {
+    dgtn::Problem prob;
+    std::vector<dgtn::Level> levels;  // levels[0] is the problem's own resolution
+    std::vector<double> matc;         // c11, c12, c44 per material (Pa)
+    double y_ref = 1;                 // modulus scale of the device arithmetic
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    dgtn_solve_opts bound_opts{};
+    bool has_opts = false;
+    size_t off_Ue = 0;
+    std::vector<std::vector<char>> staging;  // host staging of FP32 uploads
+    dgtn::SolverState* solver = nullptr;
+    ~dgtn_ctx();
+};
+
+namespace dgtn {
+
+template <typename R>
+LevelView<R> view_of(const dgtn_ctx* c, const Level& L);
+template <typename R>
+R* tau_of(const dgtn_ctx* c, const Level& L);
+
+template <typename R>
+hipError_t launch_traction(const LevelView<R>& L, const R* u, R* tau, hipStream_t s);
+template <typename R>
+hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s);
+hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
+                      double* b, hipStream_t s);
+hipError_t launch_energy(const LevelView<double>& L, const double* u, double* Ue, hipStream_t s);
+
+// solver.hip
+dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts);
+void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay);
+dgtn_status bind_solver(dgtn_ctx* c, hipStream_t s);
+
+}  // namespace dgtn

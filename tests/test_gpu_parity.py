@@ -1,0 +1,127 @@
+"""GPU parity of the HIP operator, load and energy with the FP64 oracle, on the
+same seeded inputs, called through the C ABI.
+
+Tolerances.  FP64: the library and the oracle differ only in summation order
+and in the rounding of independently computed geometry, so each entry of A u
+agrees to a small multiple of machine epsilon times the largest entry (the
+penalty terms dominate): 1e-12 of max|A u|.  FP32: the same arithmetic in
+single precision; rounding of the penalty-dominated sums allows 2e-5 of
+max|A u| entrywise and 1e-5 normwise.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dg
+
+torch = pytest.importorskip("torch")
+import paper_2111_06893_amd as dgtn  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_ENTRY = 2e-5
+TOL32_NORM = 1e-5
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype=dtype)
+
+
+def _cases():
+    mats = [W.FUSED_SILICA, W.CRYSTAL_A, W.COATING_ISO]
+    lay3 = [{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
+            {"thickness": 0.02, "n_elem": 2, "ratio": 1.5, "material": 2},
+            {"thickness": 0.93, "n_elem": 2, "ratio": 3.0, "material": 0}]
+    out = {
+        "config1": W.config1(),
+        "config4": W.config4(),
+        "box_p1_all_dirichlet": W.box(nx=2, ny=3, p=1, materials=mats, layers=lay3,
+                                      bc={"top": 1, "bottom": 1, "side": 1}),
+        "box_p2_pressure_sides": W.box(nx=3, ny=1, p=2, materials=mats, layers=lay3,
+                                       bc={"top": 2, "bottom": 1, "side": 2}),
+        "box_p7_free": W.box(nx=1, ny=2, p=7, materials=mats, layers=lay3[:2],
+                             bc={"top": 3, "bottom": 3, "side": 3}),
+        "cyl_refine0_p4_cubic": dict(W.config1(), refine=0, p=4,
+                                     materials=[W.CRYSTAL_A, W.CRYSTAL_B],
+                                     layers=[{"thickness": 0.3, "n_elem": 2, "ratio": 1.2, "material": 0},
+                                             {"thickness": 0.7, "n_elem": 1, "ratio": 1, "material": 1}]),
+    }
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_apply_fp64_matches_oracle(name):
+    spec = CASES[name]
+    print(f"[parity] apply fp64 {name} dof={W.n_dof(spec)}", flush=True)
+    P = dgtn.Problem(spec)
+    u = W.random_field(spec, seed=11)
+    ref = dg.apply(dg.Problem(spec), u)
+    got = P.apply(_dev(u)).cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= TOL64 * scale
+
+
+@pytest.mark.parametrize("name", ["config1", "box_p2_pressure_sides", "cyl_refine0_p4_cubic"])
+def test_apply_fp32_matches_oracle(name):
+    spec = CASES[name]
+    print(f"[parity] apply fp32 {name}", flush=True)
+    P = dgtn.Problem(spec)
+    u = W.random_field(spec, seed=12).astype(np.float32)
+    ref = dg.apply(dg.Problem(spec), u.astype(np.float64))
+    got = P.apply(_dev(u, torch.float32)).double().cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= TOL32_ENTRY * scale
+    assert np.linalg.norm(got - ref) <= TOL32_NORM * np.linalg.norm(ref)
+
+
+def test_apply_config2_full_size_matches_oracle():
+    """2,058,000 DoF (2000 elements, p = 6) in the launch configuration the
+    benchmark times; every output entry compared."""
+    spec = W.config2()
+    print("[parity] apply fp64 config2 full size", flush=True)
+    P = dgtn.Problem(spec)
+    u = W.random_field(spec, seed=0)
+    ref = dg.apply(dg.Problem(spec), u)
+    got = P.apply(_dev(u)).cpu().numpy()
+    assert np.abs(got - ref).max() <= TOL64 * np.abs(ref).max()
+    got32 = P.apply(_dev(u, torch.float32)).double().cpu().numpy()
+    assert np.linalg.norm(got32 - ref) <= TOL32_NORM * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["config1", "box_p2_pressure_sides"])
+def test_rhs_and_energy_match_oracle(name):
+    spec = CASES[name]
+    print(f"[parity] rhs/energy {name}", flush=True)
+    P = dgtn.Problem(spec)
+    O = dg.Problem(spec)
+    b = P.rhs().cpu().numpy()
+    bref = dg.rhs(O)
+    assert np.abs(b - bref).max() <= 1e-13 * np.abs(bref).max()
+    u = W.random_field(spec, seed=13) * 1e-9
+    U = P.energy(_dev(u))
+    Uref = dg.energy_layers(O, u)
+    np.testing.assert_allclose(U, Uref, rtol=1e-12)
+
+
+def test_rigid_modes_in_nullspace_all_neumann():
+    spec = CASES["box_p7_free"]
+    P = dgtn.Problem(spec)
+    xyz = dg.Problem(spec).mesh.xyz
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    u = np.stack([-y + 0.3 * z, x, -0.3 * x], axis=1)
+    got = P.apply(_dev(u)).cpu().numpy()
+    ref_scale = np.abs(dg.apply(dg.Problem(spec), W.random_field(spec, 1))).max()
+    assert np.abs(got).max() < 1e-13 * ref_scale
+
+
+def test_apply_is_deterministic():
+    spec = W.config1()
+    P = dgtn.Problem(spec)
+    u = _dev(W.random_field(spec, 3))
+    a = P.apply(u)
+    b = P.apply(u)
+    assert torch.equal(a, b)

@@ -1,0 +1,79 @@
+"""Host-side checks of the HIP library (no GPU): it loads, exports every symbol
+the header declares, validates its inputs, and its mesh agrees with the
+oracle's independently built mesh."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+import paper_2111_06893_amd as dgtn
+from paper_2111_06893_amd import _lib
+from oracle import mesh as omesh, physics
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dgtn.load()
+    names = _lib.header_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(_lib._SIGS) >= set(names)
+
+
+@pytest.mark.parametrize("make", [W.config1, W.config2, W.config4,
+                                  lambda: W.box(nx=3, ny=2, Lx=1.5, Ly=0.8, p=4,
+                                                layers=[{"thickness": 0.3, "n_elem": 3, "ratio": 1.7,
+                                                         "material": 0}])])
+def test_mesh_matches_oracle(make):
+    spec = make()
+    if spec["p"] > 5:
+        spec["p"] = 3  # keep the oracle mesh small; the topology is unchanged
+    P = dgtn.Problem(spec)
+    assert P.shape == W.field_shape(spec)
+    assert P.n_dof == W.n_dof(spec)
+    xyz = P.node_coords()
+    ref = omesh.build(spec).xyz
+    assert np.abs(xyz - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_config_sizes():
+    assert W.n_dof(W.config1()) == 25920
+    assert W.n_dof(W.config2()) == 2058000
+    assert W.n_elements(W.config5()) == 8000
+
+
+def test_invalid_problems_are_rejected():
+    bad = W.config1()
+    bad["p"] = 0
+    with pytest.raises(dgtn.DgtnError, match="EINVAL"):
+        dgtn.Problem(bad)
+    bad = W.config1()
+    bad["materials"] = [{"kind": "cubic", "c11": 50e9, "c12": 60e9, "c44": 30e9}]
+    with pytest.raises(dgtn.DgtnError, match="positive definite"):
+        dgtn.Problem(bad)
+    bad = W.config1()
+    bad["layers"][0]["thickness"] = -1.0
+    with pytest.raises(dgtn.DgtnError):
+        dgtn.Problem(bad)
+    bad = W.config1()
+    bad["layers"][0]["material"] = 3
+    with pytest.raises(dgtn.DgtnError):
+        dgtn.Problem(bad)
+
+
+def test_noise_psd_matches_oracle_formula():
+    U = [2.4e-11, 1.7e-13]
+    phi = [1e-6, 4e-4]
+    a = dgtn.noise_psd(U, phi, 295.0, 100.0, 1.0)
+    b = physics.noise_psd(U, phi, 295.0, 100.0, 1.0)
+    assert abs(a / b - 1) < 1e-14
+    with pytest.raises(dgtn.DgtnError):
+        dgtn.noise_psd(U, phi, -1.0, 100.0, 1.0)
+
+
+def test_workspace_size_is_reported():
+    P = dgtn.Problem(W.config1())
+    n = P.workspace_bytes()
+    # at least the two face-traction buffers (FP64 + FP32)
+    assert n > 40 * 6 * 3 * 36 * 12
