@@ -109,7 +109,7 @@ typedef struct {
  * preconditioned by a multigrid V-cycle whose levels run in
  * precond_precision (64 or 32 bit); every restart recomputes the FP64 true
  * residual (iterative refinement when the preconditioner is FP32).
- * mg_levels = 1 uses the smoother alone. */
+ * mg_levels = 1 uses the smoother alone, 0 no preconditioner. */
 typedef struct {
     int precond_precision;    /* 64 or 32                                      */
     int restart;              /* FGMRES restart length m (1..200)              */
@@ -118,7 +118,18 @@ typedef struct {
     int mg_levels;            /* levels of the V-cycle (1 = smoother only)      */
     int smooth_steps;         /* pre- and post-smoothing sweeps per level       */
     double smooth_damping;    /* damping of the additive Schwarz smoother      */
+    int smoother;             /* Schwarz subdomains: DGTN_SMOOTH_ELEMENT or DGTN_SMOOTH_COLUMN */
+    int krylov;               /* DGTN_KRYLOV_FGMRES or DGTN_KRYLOV_FCG          */
 } dgtn_solve_opts;
+
+/* Additive-Schwarz subdomains: one element, or one whole z-column of elements
+ * (all layers under one 2D column), each solved by fast diagonalisation of a
+ * separable approximation of its block. */
+enum { DGTN_SMOOTH_ELEMENT = 0, DGTN_SMOOTH_COLUMN = 1 };
+/* Outer Krylov method in FP64: restarted flexible GMRES (the paper's GMRES,
+ * flexible so that the preconditioner may vary), or flexible conjugate
+ * gradients (A is symmetric positive definite with a Dirichlet face). */
+enum { DGTN_KRYLOV_FGMRES = 0, DGTN_KRYLOV_FCG = 1 };
 
 typedef struct {
     int iters;
@@ -156,6 +167,14 @@ dgtn_status dgtn_bind(dgtn_ctx* ctx, void* workspace, size_t bytes,
 dgtn_status dgtn_apply(dgtn_ctx* ctx, int precision, const void* u, void* Au,
                        hipStream_t stream);
 
+/* One pass of dgtn_apply, for timing each kernel on its own: stage 1 runs
+ * the face-traction pass (n . Y . D u on every element face node, into the
+ * workspace face buffer), stage 2 the volume-and-flux pass that reads that
+ * buffer and writes Au, stage 3 both (= dgtn_apply).  Stage 2 alone is only
+ * meaningful after a stage 1 on the same u. */
+dgtn_status dgtn_apply_stage(dgtn_ctx* ctx, int precision, int stage, const void* u, void* Au,
+                             hipStream_t stream);
+
 /* b = load vector of the Gaussian pressure (eq. laserbeam, scaled by F0) on
  * the DGTN_BC_PRESSURE faces, entering through the Neumann flux of eq. bc
  * (device, double, n_dof). */
@@ -166,6 +185,13 @@ dgtn_status dgtn_rhs(dgtn_ctx* ctx, double* b, hipStream_t stream);
  * (u then holds the last iterate), DGTN_ENAN on a NaN/Inf. */
 dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* b,
                        double* u, dgtn_solve_stats* stats, hipStream_t stream);
+
+/* z = M^{-1} v: one application of the solver's preconditioner (the V-cycle
+ * of dgtn_solve with the same options, in opts->precond_precision), for the
+ * operator scaled by 1 / y_ref.  v, z: device double arrays of n_dof values,
+ * not aliased.  The workspace must have been bound with the same options. */
+dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* v, double* z,
+                              hipStream_t stream);
 
 /* Elastic energy per layer, U_k = 1/2 sum over the elements of layer k of
  * int S_ij Y^ijkl S_kl dV with the unlifted strain S = D_(i u_j) and LGL
@@ -180,6 +206,19 @@ dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers,
  * host function. */
 dgtn_status dgtn_noise_psd(const double* U_layers, const double* phi, int n_layers,
                            double T, double f, double F0, double* S_x);
+
+/* Introspection of the multigrid hierarchy built for `opts` (host only, no
+ * workspace needed).  dgtn_level_info returns, for level l (0 = finest), its
+ * LGL point count N, element count and column count, or DGTN_EINVAL past the
+ * coarsest level.  dgtn_smoother_block copies the additive-Schwarz subdomain
+ * data of element e on level l: for component c and reference direction d
+ * (index 3c + d), N*N entries S[node][mode] (the M-orthonormal eigenvectors of
+ * the 1D element operator) followed by N eigenvalues scaled by the modulus,
+ * 9 (N*N + N) doubles in all. */
+dgtn_status dgtn_level_info(dgtn_ctx* ctx, const dgtn_solve_opts* opts, int level, int* N,
+                            int* n_elem, int* n_cols);
+dgtn_status dgtn_smoother_block(dgtn_ctx* ctx, const dgtn_solve_opts* opts, int level, int elem,
+                                double* out);
 
 /* Node coordinates (host, double, [E][3][N^3]) of the library's mesh. */
 dgtn_status dgtn_node_coords(const dgtn_ctx* ctx, double* xyz);

@@ -51,7 +51,7 @@ def pcg(prob, b, rtol=1e-13, maxit=20000, precond=None, x0=None, verbose=False,
     it = 0
     rel = np.sqrt(np.sum(r * r)) / bn
     best, best_it = rel, 0
-    while rel > rtol and it < maxit and it - best_it < stall:
+    while rel > rtol and it < maxit and not (best < 1e-9 and it - best_it > stall):
         Ap = dg.apply(prob, p)
         alpha = rz / np.sum(p * Ap)
         x += alpha * p

@@ -47,7 +47,7 @@ def problem_struct(spec):
 
 def default_opts(precision=64, **kw):
     o = dict(precond_precision=precision, restart=30, max_iter=20000, rtol=1e-11,
-             mg_levels=1, smooth_steps=1, smooth_damping=1.0)
+             mg_levels=1, smooth_steps=1, smooth_damping=1.0, smoother=1, krylov=1)
     o.update(kw)
     return _lib.SolveOpts(**o)
 
@@ -151,6 +151,17 @@ class Problem:
                                   ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
+    def apply_stage(self, u, out, stage):
+        """One kernel pass of the apply (1 traction, 2 volume-and-flux, 3 both)."""
+        import torch
+        self._ensure()
+        prec = 64 if u.dtype == torch.float64 else 32
+        self._check_field(u, u.dtype)
+        self._check_field(out, u.dtype)
+        check(self.lib.dgtn_apply_stage(self.ctx, prec, stage, ctypes.c_void_p(u.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
     def rhs(self, out=None):
         import torch
         self._ensure()
@@ -170,7 +181,7 @@ class Problem:
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
         return out
 
-    def solve(self, b=None, u0=None, opts=None):
+    def solve(self, b=None, u0=None, opts=None, raise_on_noconv=True):
         """Solves A u = b (b defaults to the load vector); returns (u, stats)."""
         import torch
         opts = opts if opts is not None else (self.opts or default_opts())
@@ -183,8 +194,39 @@ class Problem:
         stats = _lib.SolveStats()
         st = self.lib.dgtn_solve(self.ctx, ctypes.byref(opts), ctypes.c_void_p(b.data_ptr()),
                                  ctypes.c_void_p(u.data_ptr()), ctypes.byref(stats), self._stream())
+        if st == -4 and not raise_on_noconv:   # DGTN_ENOCONV: u holds the last iterate
+            stats.converged = False
+            return u, stats
         check(st)
+        stats.converged = True
         return u, stats
+
+    def precondition(self, v, opts=None):
+        """One V-cycle z = M^{-1} v (for the operator divided by y_ref)."""
+        import torch
+        opts = opts if opts is not None else self.opts
+        if self.ws is None or self.opts is None or self.workspace_bytes(opts) > self.ws.numel():
+            self.bind(opts)
+        self._check_field(v, torch.float64)
+        z = torch.empty_like(v)
+        check(self.lib.dgtn_precondition(self.ctx, ctypes.byref(opts), ctypes.c_void_p(v.data_ptr()),
+                                         ctypes.c_void_p(z.data_ptr()), self._stream()))
+        return z
+
+    def level_info(self, opts, level):
+        N, E, C = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(self.lib.dgtn_level_info(self.ctx, ctypes.byref(opts), level, ctypes.byref(N), ctypes.byref(E),
+                                       ctypes.byref(C)))
+        return N.value, E.value, C.value
+
+    def smoother_block(self, opts, level, elem):
+        """Schwarz subdomain data of one element: arrays S[c][d] (N x N) and lam[c][d] (N)."""
+        N, _, _ = self.level_info(opts, level)
+        out = np.zeros(9 * (N * N + N))
+        check(self.lib.dgtn_smoother_block(self.ctx, ctypes.byref(opts), level, elem,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        out = out.reshape(3, 3, N * N + N)
+        return out[:, :, :N * N].reshape(3, 3, N, N), out[:, :, N * N:]
 
     def noise(self, U_layers, phi, T, f):
         return noise_psd(U_layers, phi, T, f, self.spec["load"]["F0"])

@@ -37,7 +37,8 @@ class Info(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precond_precision", c_int), ("restart", c_int), ("max_iter", c_int), ("rtol", c_double),
-                ("mg_levels", c_int), ("smooth_steps", c_int), ("smooth_damping", c_double)]
+                ("mg_levels", c_int), ("smooth_steps", c_int), ("smooth_damping", c_double),
+                ("smoother", c_int), ("krylov", c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -51,11 +52,15 @@ _SIGS = {
     "dgtn_workspace_bytes": (c_int, [c_void_p, P(SolveOpts), P(c_size_t)]),
     "dgtn_bind": (c_int, [c_void_p, c_void_p, c_size_t, P(SolveOpts), c_void_p]),
     "dgtn_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "dgtn_apply_stage": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "dgtn_rhs": (c_int, [c_void_p, c_void_p, c_void_p]),
     "dgtn_solve": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, P(SolveStats), c_void_p]),
+    "dgtn_precondition": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, c_void_p]),
     "dgtn_energy": (c_int, [c_void_p, c_void_p, P(c_double), c_void_p]),
     "dgtn_noise_psd": (c_int, [P(c_double), P(c_double), c_int, c_double, c_double, c_double, P(c_double)]),
     "dgtn_node_coords": (c_int, [c_void_p, P(c_double)]),
+    "dgtn_level_info": (c_int, [c_void_p, P(SolveOpts), c_int, P(c_int), P(c_int), P(c_int)]),
+    "dgtn_smoother_block": (c_int, [c_void_p, P(SolveOpts), c_int, c_int, P(c_double)]),
     "dgtn_destroy": (None, [c_void_p]),
     "dgtn_last_error": (ctypes.c_char_p, []),
 }

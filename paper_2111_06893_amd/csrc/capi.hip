@@ -43,7 +43,7 @@ LevelView<R> view_of(const dgtn_ctx* c, const Level& L) {
     v.w = reinterpret_cast<const R*>(b + L.off_w[pi]);
     v.bc_top = c->prob.bc_top;
     v.bc_bottom = c->prob.bc_bottom;
-    v.penalty_n2 = R(c->prob.penalty * L.N * L.N);
+    v.penalty_n2 = R(L.pen_z);
     return v;
 }
 template LevelView<double> view_of<double>(const dgtn_ctx*, const Level&);
@@ -174,7 +174,7 @@ dgtn_status dgtn_create(const dgtn_problem* p, dgtn_ctx** out) {
         c->matc = material_constants(P);
         c->y_ref = 0;
         for (size_t m = 0; m < c->matc.size(); m += 3) c->y_ref = std::max(c->y_ref, c->matc[m]);
-        c->levels.push_back(build_level(P, P.p, P.refine));
+        c->levels.push_back(build_level(P, P.p, P.refine, P.p, P.refine));
     } catch (const std::exception& ex) {
         set_error(std::string("mesh: ") + ex.what());
         delete c;
@@ -271,24 +271,31 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
     return DGTN_OK;
 }
 
-dgtn_status dgtn_apply(dgtn_ctx* c, int precision, const void* u, void* Au, hipStream_t s) {
+dgtn_status dgtn_apply_stage(dgtn_ctx* c, int precision, int stage, const void* u, void* Au, hipStream_t s) {
     if (!c || !u || !Au) { set_error("null argument"); return DGTN_EINVAL; }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     if (u == Au) { set_error("u and Au must not alias"); return DGTN_EINVAL; }
+    if (stage < 1 || stage > 3) { set_error("stage must be 1, 2 or 3"); return DGTN_EINVAL; }
     const Level& L = c->levels[0];
     if (precision == 64) {
         auto v = view_of<double>(c, L);
-        HIP_CHECK(launch_traction<double>(v, (const double*)u, tau_of<double>(c, L), s));
-        HIP_CHECK(launch_apply<double>(v, (const double*)u, tau_of<double>(c, L), (double*)Au, c->y_ref, s));
+        if (stage & 1) HIP_CHECK(launch_traction<double>(v, (const double*)u, tau_of<double>(c, L), s));
+        if (stage & 2)
+            HIP_CHECK(launch_apply<double>(v, (const double*)u, tau_of<double>(c, L), (double*)Au, c->y_ref, s));
     } else if (precision == 32) {
         auto v = view_of<float>(c, L);
-        HIP_CHECK(launch_traction<float>(v, (const float*)u, tau_of<float>(c, L), s));
-        HIP_CHECK(launch_apply<float>(v, (const float*)u, tau_of<float>(c, L), (float*)Au, (float)c->y_ref, s));
+        if (stage & 1) HIP_CHECK(launch_traction<float>(v, (const float*)u, tau_of<float>(c, L), s));
+        if (stage & 2)
+            HIP_CHECK(launch_apply<float>(v, (const float*)u, tau_of<float>(c, L), (float*)Au, (float)c->y_ref, s));
     } else {
         set_error("precision must be 64 or 32");
         return DGTN_EINVAL;
     }
     return DGTN_OK;
+}
+
+dgtn_status dgtn_apply(dgtn_ctx* c, int precision, const void* u, void* Au, hipStream_t s) {
+    return dgtn_apply_stage(c, precision, 3, u, Au, s);
 }
 
 dgtn_status dgtn_rhs(dgtn_ctx* c, double* b, hipStream_t s) {

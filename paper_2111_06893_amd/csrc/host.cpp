@@ -166,9 +166,10 @@ std::vector<double> material_constants(const Problem& P) {
     return c;
 }
 
-Level build_level(const Problem& P, int p, int refine) {
+Level build_level(const Problem& P, int p, int refine, int p0, int r0) {
     Level L;
     L.N = p + 1;
+    L.pen_z = P.penalty * (p0 + 1.0) * (p0 + 1.0);
     L.refine = refine;
     const int N = L.N, N2 = N * N;
     L.lgl = make_lgl(N);
@@ -298,7 +299,7 @@ Level build_level(const Problem& P, int p, int refine) {
         return 2.0 / std::hypot(g[m * N2 + q], g[(m + 1) * N2 + q]);
     };
     L.sig_side.assign((size_t)L.n_cols * 4 * N, 0.0);
-    const double cn2 = P.penalty * N * N;
+    const double cn2 = L.pen_z * double(1 << (r0 - refine));
     for (int c = 0; c < L.n_cols; ++c)
         for (int f = 0; f < 4; ++f)
             for (int t = 0; t < N; ++t) {

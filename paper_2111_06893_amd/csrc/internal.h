@@ -43,6 +43,7 @@ struct LevelView {
 // Host description of one level (mesh + geometry), built from the problem.
 struct Level {
     int N = 0, refine = 0, n_cols = 0, n_z = 0, E = 0;
+    double pen_z = 0;    // C (p0 + 1)^2 of the finest level, used on every level
     Lgl lgl;
     std::vector<double> geo2, xy, sig_side;
     std::vector<int> cnbr, cnf;
@@ -67,8 +68,12 @@ struct Problem {
 };
 
 // Builds the level of polynomial degree p with `refine` horizontal splits.
-// Throws std::runtime_error with a message on invalid meshes.
-Level build_level(const Problem& prob, int p, int refine);
+// The penalty of eq. penalty is that of the finest level (degree p0,
+// refinement r0) on every level: C (p0 + 1)^2 / h on z-faces, and on side
+// faces with the width of the finest columns (h / 2^(r0 - refine)), so that a
+// coarse level's penalty matches the fine operator restricted to coarse
+// functions.  Throws std::runtime_error with a message on invalid meshes.
+Level build_level(const Problem& prob, int p, int refine, int p0, int r0);
 
 // Cubic constants (c11, c12, c44) of each material in Pa.
 std::vector<double> material_constants(const Problem& prob);

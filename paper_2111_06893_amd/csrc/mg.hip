@@ -1,0 +1,727 @@
+// gfx950 kernels of the preconditioner and of the Krylov vector algebra.
+//
+//  * k_fdm_smooth   one damped additive-Schwarz sweep with one subdomain per
+//                   element; the subdomain solve is the fast-diagonalisation
+//                   inverse of a separable approximation of the element block
+//                   (per component c: sum_d kappa_cd K_d (x) M (x) M), applied
+//                   as six 1D contractions with the per-element eigenvectors.
+//  * k_prolong_p / k_restrict_p   polynomial-degree transfers (tensor-product
+//                   Lagrange interpolation between LGL grids, and its transpose).
+//  * k_prolong_h / k_restrict_h   transfers between a column and its 2 x 2
+//                   children (z unchanged).
+//  * dense coarse solve: Gauss-Jordan inversion steps and a matrix-vector product.
+//  * vector algebra for FGMRES: fused multi-dot, multi-axpy, casts.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "mg.h"
+
+namespace dgtn {
+
+namespace {
+
+template <int N>
+constexpr int nthreads() {
+    return ((N * N * N + 63) / 64) * 64;
+}
+
+// z = x + omega * FDM^{-1} (b - Ax), per element.  Ax == nullptr means x = 0
+// (first sweep from a zero guess): z = omega FDM^{-1} b.
+template <int N, typename R>
+__global__ __launch_bounds__(nthreads<N>()) void k_fdm_smooth(int E, const R* __restrict__ fdm,
+                                                              const R* __restrict__ b, const R* __restrict__ Ax,
+                                                              R* __restrict__ x, R omega) {
+    constexpr int N2 = N * N, N3 = N2 * N, PER = N2 + N;  // per (c, d): S then lambda
+    __shared__ R sr[3 * N3];
+    __shared__ R st[3 * N3];
+    __shared__ R sS[9 * PER];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const size_t base = (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) sr[q] = Ax ? b[base + q] - Ax[base + q] : b[base + q];
+    const R* fe = fdm + (size_t)e * 9 * PER;
+    for (int q = tid; q < 9 * PER; q += blockDim.x) sS[q] = fe[q];
+    __syncthreads();
+    const bool act = tid < N3;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    // t = (S_x^T (x) S_y^T (x) S_z^T) r, one direction at a time
+    // direction x: t[c][k][j][a] = sum_i S_x[i][a] r[c][k][j][i]
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 0) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[a * N + i] * sr[c * N3 + k * N2 + j * N + a];
+            st[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 1) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[a * N + j] * st[c * N3 + k * N2 + a * N + i];
+            sr[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 2) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[a * N + k] * sr[c * N3 + a * N2 + j * N + i];
+            const R lam = sS[(c * 3 + 0) * PER + N2 + i] + sS[(c * 3 + 1) * PER + N2 + j] +
+                          sS[(c * 3 + 2) * PER + N2 + k];
+            st[c * N3 + tid] = acc / lam;
+        }
+    }
+    __syncthreads();
+    // back: z = (S_x (x) S_y (x) S_z) t
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 2) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[k * N + a] * st[c * N3 + a * N2 + j * N + i];
+            sr[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 1) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[j * N + a] * sr[c * N3 + k * N2 + a * N + i];
+            st[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R* S = sS + (c * 3 + 0) * PER;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += S[i * N + a] * st[c * N3 + k * N2 + j * N + a];
+            const size_t o = base + c * N3 + tid;
+            x[o] = (Ax ? x[o] : R(0)) + omega * acc;
+        }
+    }
+}
+
+// ---- column smoother ------------------------------------------------------------
+// Forward x/y transform of r = b - Ax (or b) per element:
+// T[c][iz*N + k][col*N2 + b*N + a] = sum_{i,j} Sx[i][a] Sy[j][b] r[c][k][j][i].
+template <int N, typename R>
+__global__ __launch_bounds__(nthreads<N>()) void k_col_fwd(int n_cols, int nzN, const R* __restrict__ S,
+                                                           const R* __restrict__ b, const R* __restrict__ Ax,
+                                                           R* __restrict__ T) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ R sr[3 * N3];
+    __shared__ R st[3 * N3];
+    __shared__ R sS[2 * N2];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int col = e % n_cols, iz = e / n_cols;
+    const size_t base = (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) sr[q] = Ax ? b[base + q] - Ax[base + q] : b[base + q];
+    for (int q = tid; q < 2 * N2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * N2 + q];
+    __syncthreads();
+    const bool act = tid < N3;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += sS[a * N + i] * sr[c * N3 + k * N2 + j * N + a];
+            st[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+        const size_t ld = (size_t)n_cols * N2;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += sS[N2 + a * N + j] * st[c * N3 + k * N2 + a * N + i];
+            T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * N2 + j * N + i] = acc;
+        }
+    }
+}
+
+// Backward x/y transform and update: x = (x or 0) + omega (Sx (x) Sy) X.
+template <int N, typename R>
+__global__ __launch_bounds__(nthreads<N>()) void k_col_bwd(int n_cols, int nzN, const R* __restrict__ S,
+                                                           const R* __restrict__ X, R* __restrict__ x, R omega,
+                                                           int accumulate) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ R sr[3 * N3];
+    __shared__ R st[3 * N3];
+    __shared__ R sS[2 * N2];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int col = e % n_cols, iz = e / n_cols;
+    const size_t ld = (size_t)n_cols * N2;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) {
+        const int c = q / N3, r = q % N3, kk = r / N2, ab = r % N2;
+        sr[q] = X[((size_t)c * nzN + iz * N + kk) * ld + (size_t)col * N2 + ab];
+    }
+    for (int q = tid; q < 2 * N2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * N2 + q];
+    __syncthreads();
+    const bool act = tid < N3;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    if (act) {  // y: st[c][k][j][a] = sum_b Sy[j][b] sr[c][k][b][a]
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R acc = 0;
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) acc += sS[N2 + j * N + bb] * sr[c * N3 + k * N2 + bb * N + i];
+            st[c * N3 + tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (act) {
+        const size_t base = (size_t)e * 3 * N3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += sS[i * N + a] * st[c * N3 + k * N2 + j * N + a];
+            const size_t o = base + c * N3 + tid;
+            x[o] = (accumulate ? x[o] : R(0)) + omega * acc;
+        }
+    }
+}
+
+// Batched (over the 3 components, blockIdx.z) tiled product along z:
+//   trans = 1:  Y[i][m] = (sum_z V[z][i] T[z][m]) / (lz[i] + rx lx_a + ry ly_b)
+//   trans = 0:  T[z][m] =  sum_i V[z][i] Y[i][m]
+// V [3][n][n] row = z node, column = mode; in/out [3][n][ncol], m = col*N2 + b*N + a.
+constexpr int kTM = 64, kTN = 64, kTK = 16;
+template <typename R>
+__global__ __launch_bounds__(256) void k_col_gemm(int n, int ncol, int N, int trans, const R* __restrict__ V,
+                                                  const R* __restrict__ in, R* __restrict__ out,
+                                                  const R* __restrict__ lz, const R* __restrict__ lam,
+                                                  const R* __restrict__ rat) {
+    __shared__ R As[kTK][kTM];
+    __shared__ R Bs[kTK][kTN];
+    const int c = blockIdx.z;
+    const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const R* Vc = V + (size_t)c * n * n;
+    const R* Bc = in + (size_t)c * n * ncol;
+    R acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+    for (int k0 = 0; k0 < n; k0 += kTK) {
+        for (int q = tid; q < kTK * kTM; q += 256) {
+            const int kk = q / kTM, rr = q % kTM;
+            const int kg = k0 + kk, rg = row0 + rr;
+            R v = 0;
+            if (kg < n && rg < n) v = trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg];
+            As[kk][rr] = v;
+        }
+        for (int q = tid; q < kTK * kTN; q += 256) {
+            const int kk = q / kTN, cc = q % kTN;
+            const int kg = k0 + kk, cg = col0 + cc;
+            Bs[kk][cc] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTK; ++kk) {
+            R a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[kk][ty * 4 + q];
+                b[q] = Bs[kk][tx * 4 + q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+        }
+        __syncthreads();
+    }
+    const int N2 = N * N;
+    R* Oc = out + (size_t)c * n * ncol;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int rg = row0 + ty * 4 + p;
+        if (rg >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cg = col0 + tx * 4 + q;
+            if (cg >= ncol) continue;
+            R v = acc[p][q];
+            if (trans) {
+                const int colm = cg / N2, ab = cg % N2, bb = ab / N, aa = ab % N;
+                const R den = lz[(size_t)c * n + rg] + rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * N + aa] +
+                              rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * N + bb];
+                v /= den;
+            }
+            Oc[(size_t)rg * ncol + cg] = v;
+        }
+    }
+}
+
+// Fine += P coarse over the same elements, P = I (x) I (x) I with I [Nf][Nc].
+template <typename R>
+__global__ void k_prolong_p(int E, int Nf, int Nc, const R* __restrict__ I, const R* __restrict__ uc,
+                            R* __restrict__ uf) {
+    __shared__ R s[3 * kMaxN * kMaxN * kMaxN];
+    __shared__ R t[3 * kMaxN * kMaxN * kMaxN];
+    __shared__ R sI[kMaxN * kMaxN];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+    for (int q = tid; q < 3 * Nc3; q += blockDim.x) s[q] = uc[(size_t)e * 3 * Nc3 + q];
+    for (int q = tid; q < Nf * Nc; q += blockDim.x) sI[q] = I[q];
+    __syncthreads();
+    // x: [c][kc][jc][if]
+    for (int q = tid; q < 3 * Nc * Nc * Nf; q += blockDim.x) {
+        const int a = q % Nf, jc = (q / Nf) % Nc, kc = (q / (Nf * Nc)) % Nc, c = q / (Nf * Nc * Nc);
+        R acc = 0;
+        for (int b = 0; b < Nc; ++b) acc += sI[a * Nc + b] * s[c * Nc3 + kc * Nc * Nc + jc * Nc + b];
+        t[q] = acc;
+    }
+    __syncthreads();
+    // y: [c][kc][jf][if]
+    for (int q = tid; q < 3 * Nc * Nf * Nf; q += blockDim.x) {
+        const int a = q % Nf, jf = (q / Nf) % Nf, kc = (q / (Nf * Nf)) % Nc, c = q / (Nf * Nf * Nc);
+        R acc = 0;
+        for (int b = 0; b < Nc; ++b) acc += sI[jf * Nc + b] * t[((c * Nc + kc) * Nc + b) * Nf + a];
+        s[q] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < 3 * Nf3; q += blockDim.x) {
+        const int a = q % Nf, jf = (q / Nf) % Nf, kf = (q / (Nf * Nf)) % Nf, c = q / Nf3;
+        R acc = 0;
+        for (int b = 0; b < Nc; ++b) acc += sI[kf * Nc + b] * s[((c * Nc + b) * Nf + jf) * Nf + a];
+        uf[(size_t)e * 3 * Nf3 + q] += acc;
+    }
+}
+
+// Coarse = P^T fine.
+template <typename R>
+__global__ void k_restrict_p(int E, int Nf, int Nc, const R* __restrict__ I, const R* __restrict__ rf,
+                             R* __restrict__ rc) {
+    __shared__ R s[3 * kMaxN * kMaxN * kMaxN];
+    __shared__ R t[3 * kMaxN * kMaxN * kMaxN];
+    __shared__ R sI[kMaxN * kMaxN];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+    for (int q = tid; q < 3 * Nf3; q += blockDim.x) s[q] = rf[(size_t)e * 3 * Nf3 + q];
+    for (int q = tid; q < Nf * Nc; q += blockDim.x) sI[q] = I[q];
+    __syncthreads();
+    // x: [c][kf][jf][ic]
+    for (int q = tid; q < 3 * Nf * Nf * Nc; q += blockDim.x) {
+        const int a = q % Nc, jf = (q / Nc) % Nf, kf = (q / (Nc * Nf)) % Nf, c = q / (Nc * Nf * Nf);
+        R acc = 0;
+        for (int b = 0; b < Nf; ++b) acc += sI[b * Nc + a] * s[c * Nf3 + kf * Nf * Nf + jf * Nf + b];
+        t[q] = acc;
+    }
+    __syncthreads();
+    // y: [c][kf][jc][ic]
+    for (int q = tid; q < 3 * Nf * Nc * Nc; q += blockDim.x) {
+        const int a = q % Nc, jc = (q / Nc) % Nc, kf = (q / (Nc * Nc)) % Nf, c = q / (Nc * Nc * Nf);
+        R acc = 0;
+        for (int b = 0; b < Nf; ++b) acc += sI[b * Nc + jc] * t[((c * Nf + kf) * Nf + b) * Nc + a];
+        s[q] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < 3 * Nc3; q += blockDim.x) {
+        const int a = q % Nc, jc = (q / Nc) % Nc, kc = (q / (Nc * Nc)) % Nc, c = q / Nc3;
+        R acc = 0;
+        for (int b = 0; b < Nf; ++b) acc += sI[b * Nc + kc] * s[((c * Nf + b) * Nc + jc) * Nc + a];
+        rc[(size_t)e * 3 * Nc3 + q] = acc;
+    }
+}
+
+// h-transfers.  Ih [2][N][N]: Ih[s][a][b] = l_b(child-s node a in parent coordinates).
+// Fine element e_f = iz * ncf + colf; parent[colf] = coarse column, child[colf] = sx + 2 sy.
+template <typename R>
+__global__ void k_prolong_h(int N, int ncf, int ncc, const int* __restrict__ parent,
+                            const int* __restrict__ child, const R* __restrict__ Ih, const R* __restrict__ uc,
+                            R* __restrict__ uf) {
+    const int ef = blockIdx.x, tid = threadIdx.x;
+    const int colf = ef % ncf, iz = ef / ncf;
+    const int ec = iz * ncc + parent[colf];
+    const int sx = child[colf] & 1, sy = child[colf] >> 1;
+    const int N2 = N * N, N3 = N2 * N;
+    const R* Ix = Ih + sx * N2;
+    const R* Iy = Ih + sy * N2;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) {
+        const int i = q % N, j = (q / N) % N, k = (q / N2) % N, c = q / N3;
+        const R* src = uc + (size_t)ec * 3 * N3 + c * N3 + k * N2;
+        R acc = 0;
+        for (int b = 0; b < N; ++b) {
+            R row = 0;
+            for (int a = 0; a < N; ++a) row += Ix[i * N + a] * src[b * N + a];
+            acc += Iy[j * N + b] * row;
+        }
+        uf[(size_t)ef * 3 * N3 + q] += acc;
+    }
+}
+
+template <typename R>
+__global__ void k_restrict_h(int N, int ncf, int ncc, const int* __restrict__ children,
+                             const R* __restrict__ Ih, const R* __restrict__ rf, R* __restrict__ rc) {
+    const int ec = blockIdx.x, tid = threadIdx.x;
+    const int colc = ec % ncc, iz = ec / ncc;
+    const int N2 = N * N, N3 = N2 * N;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) {
+        const int ic = q % N, jc = (q / N) % N, k = (q / N2) % N, c = q / N3;
+        R acc = 0;
+        for (int s = 0; s < 4; ++s) {
+            const int ef = iz * ncf + children[colc * 4 + s];
+            const R* Ix = Ih + (s & 1) * N2;
+            const R* Iy = Ih + (s >> 1) * N2;
+            const R* src = rf + (size_t)ef * 3 * N3 + c * N3 + k * N2;
+            for (int j = 0; j < N; ++j) {
+                R row = 0;
+                for (int i = 0; i < N; ++i) row += Ix[i * N + ic] * src[j * N + i];
+                acc += Iy[j * N + jc] * row;
+            }
+        }
+        rc[(size_t)ec * 3 * N3 + q] = acc;
+    }
+}
+
+// ---- dense coarse solve ------------------------------------------------------
+
+__global__ void k_set_unit(double* e, int j) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (j > 0) e[j - 1] = 0.0;
+        e[j] = 1.0;
+    }
+}
+
+// Gauss-Jordan step k on the n x n matrix A (in place -> inverse).  Stage 1
+// saves column k, stage 2 scales row k by 1/A[k][k] (A[k][k] replaced by 1).
+__global__ void k_gj_savecol(const double* A, double* col, int n, int k) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) col[j] = A[(size_t)j * n + k];
+}
+
+__global__ void k_gj_row(double* A, const double* col, int n, int k) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double piv = col[k];
+    const double v = (j == k) ? 1.0 : A[(size_t)k * n + j];
+    A[(size_t)k * n + j] = v / piv;
+}
+
+// stage 2: A[i][j] -= col[i] * A[k][j] for i != k; column k of other rows becomes -col[i] * (1/piv).
+__global__ void k_gj_update(double* A, const double* col, int n, int k) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n || i == k) return;
+    const double f = col[i];
+    const double akj = A[(size_t)k * n + j];
+    if (j == k) A[(size_t)i * n + j] = -f * akj;
+    else A[(size_t)i * n + j] -= f * akj;
+}
+
+// y = A x, one 64-lane wave per row, fixed-order reduction.
+template <typename R>
+__global__ void k_gemv(const R* __restrict__ A, const R* __restrict__ x, R* __restrict__ y, int n) {
+    const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (row >= n) return;
+    R acc = 0;
+    const R* a = A + (size_t)row * n;
+    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) y[row] = acc;
+}
+
+template <typename R>
+__global__ void k_zero(R* x, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) x[q] = R(0);
+}
+
+template <typename A, typename B>
+__global__ void k_cast(const A* __restrict__ x, B* __restrict__ y, size_t n, double scale) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = (B)((double)x[q] * scale);
+}
+
+// y = b - y
+template <typename R>
+__global__ void k_resid(const R* __restrict__ b, R* __restrict__ y, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = b[q] - y[q];
+}
+
+// partial[v][blk] = sum over the block's slice of V_v . w, for v < nv; the
+// last slot (v == nv) holds w . w.  Fixed order: deterministic.
+constexpr int kDotThreads = 256;
+__global__ __launch_bounds__(kDotThreads) void k_multidot(const double* __restrict__ V, size_t ldv, int nv,
+                                                          const double* __restrict__ w, size_t n,
+                                                          double* __restrict__ partial, int nblk) {
+    __shared__ double red[kDotThreads];
+    const int tid = threadIdx.x;
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int v = 0; v <= nv; ++v) {
+        const double* a = (v < nv) ? V + (size_t)v * ldv : w;
+        double acc = 0;
+        for (size_t q = lo + tid; q < hi; q += kDotThreads) acc += a[q] * w[q];
+        red[tid] = acc;
+        __syncthreads();
+        for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) partial[(size_t)v * nblk + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > nv) return;
+    double acc = 0;
+    for (int b = 0; b < nblk; ++b) acc += partial[(size_t)v * nblk + b];
+    out[v] = acc;
+}
+
+// w += sum_v coef[v] V_v   (coef on the device)
+__global__ void k_multiaxpy(double* __restrict__ w, const double* __restrict__ V, size_t ldv, int nv,
+                            const double* __restrict__ coef, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    double acc = w[q];
+    for (int v = 0; v < nv; ++v) acc += coef[v] * V[(size_t)v * ldv + q];
+    w[q] = acc;
+}
+
+__global__ void k_scale_copy(const double* __restrict__ x, double* __restrict__ y, double s, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = s * x[q];
+}
+
+// y += a x
+__global__ void k_axpy(double* __restrict__ y, double a, const double* __restrict__ x, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] += a * x[q];
+}
+
+// p = z + beta p
+__global__ void k_xpby(double* __restrict__ p, const double* __restrict__ z, double beta, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = z[q] + beta * p[q];
+}
+
+struct DotPairs {
+    const double* x[4];
+    const double* y[4];
+    int np;
+};
+
+// partial[v][blk] = x_v . y_v over the block's slice (fixed order).
+__global__ __launch_bounds__(kDotThreads) void k_dotpairs(DotPairs d, size_t n, double* __restrict__ partial,
+                                                          int nblk) {
+    __shared__ double red[kDotThreads];
+    const int tid = threadIdx.x;
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int v = 0; v < d.np; ++v) {
+        double acc = 0;
+        for (size_t q = lo + tid; q < hi; q += kDotThreads) acc += d.x[v][q] * d.y[v][q];
+        red[tid] = acc;
+        __syncthreads();
+        for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) partial[(size_t)v * nblk + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+inline unsigned blocks_for(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename F>
+hipError_t dispatch(int N, F&& f) {
+    switch (N) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t mg_smooth(int N, int E, const R* fdm, const R* b, const R* Ax, R* x, R omega, hipStream_t s) {
+    return dispatch(N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_fdm_smooth<NN, R>), dim3(E), dim3(nthreads<NN>()), 0, s, E, fdm, b, Ax, x, omega);
+        return hipGetLastError();
+    });
+}
+
+template <typename R>
+hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, const R* rat, const R* V,
+                         const R* lz, const R* b, const R* Ax, R* x, R omega, R* T, R* Y, hipStream_t s) {
+    const int E = n_cols * n_z, n = n_z * N, ncol = n_cols * N * N;
+    hipError_t err = dispatch(N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_col_fwd<NN, R>), dim3(E), dim3(nthreads<NN>()), 0, s, n_cols, n, S, b, Ax, T);
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    const dim3 grid((ncol + kTN - 1) / kTN, (n + kTM - 1) / kTM, 3);
+    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, N, 1, V, T, Y, lz, lam, rat);
+    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, N, 0, V, Y, T, lz, lam, rat);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    return dispatch(N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_col_bwd<NN, R>), dim3(E), dim3(nthreads<NN>()), 0, s, n_cols, n, S, T, x, omega,
+                           Ax ? 1 : 0);
+        return hipGetLastError();
+    });
+}
+
+template <typename R>
+hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, uc, uf);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t mg_restrict_p(int E, int Nf, int Nc, const R* I, const R* rf, R* rc, hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, rf, rc);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t mg_prolong_h(int N, int Ef, int ncf, int ncc, const int* parent, const int* child, const R* Ih,
+                        const R* uc, R* uf, hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong_h<R>), dim3(Ef), dim3(256), 0, s, N, ncf, ncc, parent, child, Ih, uc, uf);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t mg_restrict_h(int N, int Ec, int ncf, int ncc, const int* children, const R* Ih, const R* rf, R* rc,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict_h<R>), dim3(Ec), dim3(256), 0, s, N, ncf, ncc, children, Ih, rf, rc);
+    return hipGetLastError();
+}
+
+hipError_t dense_set_unit(double* e, int j, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_unit, dim3(1), dim3(64), 0, s, e, j);
+    return hipGetLastError();
+}
+
+hipError_t dense_invert(double* A, double* col, int n, hipStream_t s) {
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_savecol, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, col, n, k);
+        hipLaunchKernelGGL(k_gj_row, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, col, n, k);
+        hipLaunchKernelGGL(k_gj_update, dim3(blocks_for(n, 256), n), dim3(256), 0, s, A, col, n, k);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t dense_gemv(const R* A, const R* x, R* y, int n, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemv<R>), dim3(blocks_for((size_t)n * 64, 256)), dim3(256), 0, s, A, x, y, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t vec_zero(R* x, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+template <typename A, typename B>
+hipError_t vec_cast(const A* x, B* y, size_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<A, B>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, n, scale);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t vec_resid(const R* b, R* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_resid<R>), dim3(blocks_for(n, 256)), dim3(256), 0, s, b, y, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_multidot(const double* V, size_t ldv, int nv, const double* w, size_t n, double* partial, int nblk,
+                        double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, nv, w, n, partial, nblk);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(nv + 1, 64)), dim3(64), 0, s, partial, nblk, nv, out);
+    return hipGetLastError();
+}
+
+hipError_t vec_multiaxpy(double* w, const double* V, size_t ldv, int nv, const double* coef, size_t n,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, V, ldv, nv, coef, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_axpy(double* y, double a, const double* x, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, y, a, x, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_xpby(double* p, const double* z, double beta, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, z, beta, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_dotpairs(int np, const double* const* x, const double* const* y, size_t n, double* partial, int nblk,
+                        double* out, hipStream_t s) {
+    DotPairs d{};
+    d.np = np;
+    for (int v = 0; v < np; ++v) {
+        d.x[v] = x[v];
+        d.y[v] = y[v];
+    }
+    hipLaunchKernelGGL(k_dotpairs, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partial, nblk, np - 1, out);
+    return hipGetLastError();
+}
+
+hipError_t vec_scale_copy(const double* x, double* y, double a, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, a, n);
+    return hipGetLastError();
+}
+
+#define INST(R)                                                                                        \
+    template hipError_t mg_smooth<R>(int, int, const R*, const R*, const R*, R*, R, hipStream_t);      \
+    template hipError_t mg_col_smooth<R>(int, int, int, const R*, const R*, const R*, const R*,         \
+                                         const R*, const R*, const R*, R*, R, R*, R*, hipStream_t);    \
+    template hipError_t mg_prolong_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);           \
+    template hipError_t mg_restrict_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);          \
+    template hipError_t mg_prolong_h<R>(int, int, int, int, const int*, const int*, const R*, const R*, \
+                                        R*, hipStream_t);                                              \
+    template hipError_t mg_restrict_h<R>(int, int, int, int, const int*, const R*, const R*, R*,       \
+                                         hipStream_t);                                                 \
+    template hipError_t dense_gemv<R>(const R*, const R*, R*, int, hipStream_t);                       \
+    template hipError_t vec_zero<R>(R*, size_t, hipStream_t);                                          \
+    template hipError_t vec_resid<R>(const R*, R*, size_t, hipStream_t);
+INST(double)
+INST(float)
+template hipError_t vec_cast<double, float>(const double*, float*, size_t, double, hipStream_t);
+template hipError_t vec_cast<float, double>(const float*, double*, size_t, double, hipStream_t);
+template hipError_t vec_cast<double, double>(const double*, double*, size_t, double, hipStream_t);
+
+}  // namespace dgtn

@@ -1,0 +1,150 @@
+"""GPU checks of the preconditioner and of the Krylov solve, through the C ABI.
+
+* One V-cycle of the library equals a NumPy V-cycle assembled from the oracle's
+  operators on the same levels (fine p = 3 and coarse p = 1 with the fine
+  level's penalty, dense coarse inverse), the library's own Schwarz subdomain
+  data and LGL interpolation: FP64 to 1e-10, FP32 to 1e-4.
+* The FP64 solve (flexible CG, column-Schwarz preconditioner) reproduces the
+  oracle's converged layer energies (stored by tests/golden/make_golden.py,
+  which calls only the oracle) to 1e-10 relative; the FP32-preconditioned
+  solve, with the FP64 residual recomputed periodically, to 1e-8.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dg, lgl
+
+torch = pytest.importorskip("torch")
+import paper_2111_06893_amd as dgtn  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "energies.json")
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype=torch.float64)
+
+
+def _golden(name):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden energies not generated")
+    data = json.load(open(GOLDEN))
+    if name not in data:
+        pytest.skip(f"no golden entry {name}")
+    return data[name]
+
+
+def _interp3(I, u):
+    """Apply I (x) I (x) I to u[E, 3, k, j, i]."""
+    u = np.einsum("ai,ecgbi->ecgba", I, u)
+    u = np.einsum("bj,ecgji->ecgbi", I, u)
+    return np.einsum("gk,eckji->ecgji", I, u)
+
+
+def _fdm_apply(P, opts, r):
+    E, _, N, _, _ = r.shape
+    out = np.zeros_like(r)
+    for e in range(E):
+        S, lam = P.smoother_block(opts, 0, e)
+        for c in range(3):
+            T = np.kron(S[c][2], np.kron(S[c][1], S[c][0]))
+            L = (lam[c][2][:, None, None] + lam[c][1][None, :, None] + lam[c][0][None, None, :]).ravel()
+            out[e, c] = (T @ ((T.T @ r[e, c].ravel()) / L)).reshape(N, N, N)
+    return out
+
+
+@pytest.mark.parametrize("nu,omega", [(1, 1.0), (2, 0.7)])
+def test_vcycle_matches_numpy_reference(nu, omega):
+    mats = [W.FUSED_SILICA, W.CRYSTAL_A]
+    spec = W.box(nx=2, ny=2, Lx=1.0, Ly=0.7, p=3, materials=mats,
+                 layers=[{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
+                         {"thickness": 0.6, "n_elem": 2, "ratio": 2.0, "material": 0}])
+    print(f"[solver] vcycle reference nu={nu} omega={omega}", flush=True)
+    P = dgtn.Problem(spec)
+    opts = dgtn.default_opts(64, mg_levels=2, smooth_steps=nu, smooth_damping=omega, smoother=0, krylov=0)
+    assert P.level_info(opts, 1)[0] == 2
+    v = W.random_field(spec, seed=21)
+    z = P.precondition(_dev(v), opts).cpu().numpy()
+    yref = P.y_ref
+    Of = dg.Problem(spec)
+    coarse = dict(spec, p=1, penalty=spec["penalty"] * (4 / 2) ** 2)
+    Oc = dg.Problem(coarse)
+    Ac = dg.assemble_dense(Oc) / yref
+    xf, _ = lgl.nodes_weights(4)
+    xc, _ = lgl.nodes_weights(2)
+    I = lgl.interp_matrix(xc, xf)
+
+    def A(x):
+        return dg.apply(Of, x) / yref
+
+    x = omega * _fdm_apply(P, opts, v)
+    for _ in range(nu - 1):
+        x = x + omega * _fdm_apply(P, opts, v - A(x))
+    r = v - A(x)
+    rc = _interp3(I.T, r)
+    ec = np.linalg.solve(Ac, rc.ravel()).reshape(rc.shape)
+    x = x + _interp3(I, ec)
+    for _ in range(nu):
+        x = x + omega * _fdm_apply(P, opts, v - A(x))
+    assert np.abs(z - x).max() <= 1e-10 * np.abs(x).max()
+    opts32 = dgtn.default_opts(32, mg_levels=2, smooth_steps=nu, smooth_damping=omega, smoother=0, krylov=0)
+    z32 = P.precondition(_dev(v), opts32).cpu().numpy()
+    assert np.abs(z32 - x).max() <= 1e-4 * np.abs(x).max()
+
+
+def _solve_energy(spec, prec, **kw):
+    P = dgtn.Problem(spec)
+    opts = dgtn.default_opts(prec, **kw)
+    u, st = P.solve(opts=opts)
+    return P.energy(u), st
+
+
+@pytest.mark.parametrize("name", ["config1", "config3_seed0", "config3_seed1", "config3_seed2"])
+def test_fp64_solve_matches_oracle_energy(name):
+    g = _golden(name)
+    print(f"[solver] fp64 solve {name}", flush=True)
+    U, st = _solve_energy(g["spec"], 64, rtol=1e-11, max_iter=8000)
+    ref = np.array(g["U_layers"])
+    assert abs(U.sum() / ref.sum() - 1) < 1e-10
+    np.testing.assert_allclose(U, ref, rtol=1e-9)
+
+
+@pytest.mark.parametrize("name", ["config1", "config3_seed0", "config3_seed1", "config3_seed2"])
+def test_mixed_precision_solve_matches_oracle_energy(name):
+    g = _golden(name)
+    print(f"[solver] fp32-preconditioned solve {name}", flush=True)
+    U, st = _solve_energy(g["spec"], 32, rtol=1e-11, max_iter=8000)
+    ref = np.array(g["U_layers"])
+    assert abs(U.sum() / ref.sum() - 1) < 1e-8
+
+
+def test_fgmres_and_fcg_agree_and_solve_reports_status():
+    spec = W.config1()
+    spec["p"] = 3
+    P = dgtn.Problem(spec)
+    u1, s1 = P.solve(opts=dgtn.default_opts(64, krylov=1, rtol=1e-11, max_iter=8000))
+    U1 = P.energy(u1)
+    u2, s2 = P.solve(opts=dgtn.default_opts(64, krylov=0, restart=60, rtol=1e-6, max_iter=20000))
+    U2 = P.energy(u2)
+    assert s1.converged and s2.converged
+    assert abs(U2.sum() / U1.sum() - 1) < 1e-5
+    # iteration cap -> DGTN_ENOCONV, reported without raising when asked
+    u3, s3 = P.solve(opts=dgtn.default_opts(64, rtol=1e-11, max_iter=5), raise_on_noconv=False)
+    assert not s3.converged and s3.iters == 5
+    with pytest.raises(dgtn.DgtnError, match="ENOCONV"):
+        P.solve(opts=dgtn.default_opts(64, rtol=1e-11, max_iter=5))
+
+
+def test_noise_from_solved_energies():
+    g = _golden("config1")
+    P = dgtn.Problem(g["spec"])
+    u, st = P.solve(opts=dgtn.default_opts(64, rtol=1e-11, max_iter=8000))
+    U = P.energy(u)
+    from oracle import physics
+    S = P.noise(U, [1e-6] * len(U), 295.0, 100.0)
+    assert abs(S / physics.noise_psd(g["U_layers"], [1e-6] * len(U), 295.0, 100.0, 1.0) - 1) < 1e-10
