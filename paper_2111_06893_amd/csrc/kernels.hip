@@ -68,7 +68,7 @@ __device__ __forceinline__ void gradient(const R* su, const R* sD, int i, int j,
                                          const NodeGeo<R>& g, R G[3][3]) {
     constexpr int N2 = N * N, N3 = N2 * N;
     const R dz = R(2) / g.hz;
-#pragma unroll
+#pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         R dxi = 0, deta = 0, dzeta = 0;
         const R* ul = su + l * N3;
@@ -181,150 +181,237 @@ __device__ __forceinline__ NodeGeo<R> node_geo(const LevelView<R>& L, int col, i
     return r;
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs; map them so that
+// each XCD processes one contiguous range of elements, whose face neighbours
+// (the next column and the next z-layer) then mostly sit in the same L2.
+__device__ __forceinline__ int xcd_element(int bid, int E) {
+    const int q = E / 8, rem = E % 8;
+    const int x = bid % 8, r = bid / 8;
+    return x * q + min(x, rem) + r;
+}
+
+// Per-face data of one element, resolved once per workgroup into LDS.
+template <typename R>
+struct FaceInfo {
+    int e, f, flip, bc;   // neighbour element, its face, orientation; bc != 0 on boundaries
+    R c11, c12, c44;      // averaged moduli on the face (own on boundaries)
+    R hz;                 // neighbour thickness (own on boundaries)
+};
+
 template <int N, typename R>
-__global__ __launch_bounds__(threads_for<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
-                                                              R* __restrict__ tau) {
-    constexpr int N2 = N * N, N3 = N2 * N;
-    __shared__ R su[3 * N3];
-    __shared__ R sD[N2];
-    const int e = blockIdx.x;
-    const int tid = threadIdx.x;
-    const R* ue = u + (size_t)e * 3 * N3;
-    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
-    __syncthreads();
-    if (tid >= N3) return;
-    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
-    const bool fi = (i == 0) | (i == N - 1), fj = (j == 0) | (j == N - 1), fk = (k == 0) | (k == N - 1);
-    if (!(fi | fj | fk)) return;
-    const int col = e % L.n_cols, iz = e / L.n_cols;
-    const NodeGeo<R> g = node_geo<N>(L, col, iz, i, j);
-    R G[3][3], S[6], T[6];
-    gradient<N>(su, sD, i, j, k, g, G);
-    sym_of(G, S);
-    const int m = L.zmat[iz];
-    cubic_stress(L.mat[3 * m], L.mat[3 * m + 1], L.mat[3 * m + 2], S, T);
-    const int faces[3] = {fi ? (i == 0 ? 0 : 1) : -1, fj ? (j == 0 ? 2 : 3) : -1, fk ? (k == 0 ? 4 : 5) : -1};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int f = faces[q];
-        if (f < 0) continue;
-        R n[3], amag, t[3];
-        face_normal(f, g, n, amag);
-        traction(n, T, t);
-        R* dst = tau + ((size_t)e * 6 + f) * 3 * N2 + face_index<N>(f, i, j, k);
-        dst[0] = t[0];
-        dst[N2] = t[1];
-        dst[2 * N2] = t[2];
+__device__ __forceinline__ void load_faces(const LevelView<R>& L, int col, int iz, int tid, FaceInfo<R>* sf,
+                                           R* sown) {
+    if (tid < 6) {
+        const Nbr nb = neighbour(L, col, iz, tid);
+        FaceInfo<R> fi;
+        fi.e = nb.e;
+        fi.f = nb.f;
+        fi.flip = nb.flip;
+        fi.bc = nb.bc;
+        const int m = L.zmat[iz];
+        const int mn = nb.bc == 0 ? L.zmat[nb.e / L.n_cols] : m;
+        fi.c11 = R(0.5) * (L.mat[3 * m] + L.mat[3 * mn]);
+        fi.c12 = R(0.5) * (L.mat[3 * m + 1] + L.mat[3 * mn + 1]);
+        fi.c44 = R(0.5) * (L.mat[3 * m + 2] + L.mat[3 * mn + 2]);
+        fi.hz = nb.bc == 0 ? L.hz[nb.e / L.n_cols] : L.hz[iz];
+        sf[tid] = fi;
+    } else if (tid == 6) {
+        const int m = L.zmat[iz];
+        sown[0] = L.mat[3 * m];
+        sown[1] = L.mat[3 * m + 1];
+        sown[2] = L.mat[3 * m + 2];
+        sown[3] = L.hz[iz];
     }
 }
 
+// Lanes per workgroup: one per node for the volume work, one per face node
+// (6 N^2) for the face work, rounded up to whole 64-wide waves.
+template <int N>
+constexpr int apply_threads() {
+    return ((((N * N * N) > (6 * N * N) ? (N * N * N) : (6 * N * N)) + 63) / 64) * 64;
+}
+
+// Node (i, j, k) of face node fi on face f (the face-buffer order).
+template <int N>
+__device__ __forceinline__ void face_node(int f, int fi, int& i, int& j, int& k) {
+    const int a = fi % N, b = fi / N;
+    const int s = (f & 1) ? N - 1 : 0;
+    if (f < 2) { i = s; j = a; k = b; }
+    else if (f < 4) { i = a; j = s; k = b; }
+    else { i = a; j = b; k = s; }
+}
+
 template <int N, typename R>
-__global__ __launch_bounds__(threads_for<N>()) void k_apply(LevelView<R> L, const R* __restrict__ u,
-                                                           const R* __restrict__ tau, R* __restrict__ out,
-                                                           R scale) {
+__global__ __launch_bounds__(apply_threads<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
+                                                                R* __restrict__ tau) {
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ R su[3 * N3];
-    __shared__ R sF[9 * N3];
+    __shared__ R sD[N2];
+    __shared__ R sown[4];
+    const int e = xcd_element(blockIdx.x, L.E);
+    const int tid = threadIdx.x;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
+    const R* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    if (tid == 0) {
+        const int m = L.zmat[iz];
+        sown[0] = L.mat[3 * m];
+        sown[1] = L.mat[3 * m + 1];
+        sown[2] = L.mat[3 * m + 2];
+        sown[3] = L.hz[iz];
+    }
+    const bool act = tid < 6 * N2;
+    const int f = tid / N2, fi = tid % N2;
+    int i = 0, j = 0, k = 0;
+    if (act) face_node<N>(f, fi, i, j, k);
+    NodeGeo<R> g = act ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
+    __syncthreads();
+    if (!act) return;
+    g.hz = sown[3];
+    R G[3][3], S[6], T[6], n[3], amag, t[3];
+    gradient<N>(su, sD, i, j, k, g, G);
+    sym_of(G, S);
+    cubic_stress(sown[0], sown[1], sown[2], S, T);
+    face_normal(f, g, n, amag);
+    traction(n, T, t);
+    R* dst = tau + ((size_t)e * 6 + f) * 3 * N2 + fi;
+    dst[0] = t[0];
+    dst[N2] = t[1];
+    dst[2 * N2] = t[2];
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, const R* __restrict__ u,
+                                                             const R* __restrict__ tau, R* __restrict__ out,
+                                                             R scale) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ R sbuf[9 * N3];        // the element's u (3 N^3), later the fluxes F (9 N^3)
+    __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
+    __shared__ R sLF[6 * 6 * N2];     // per face node: lift of the auxiliary-variable flux into S
     __shared__ R sD[N2];
     __shared__ R sw[N];
-    const int e = blockIdx.x;
+    __shared__ FaceInfo<R> sface[6];
+    __shared__ R sown[4];
+    R* su = sbuf;
+    const int e = xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
     for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
     for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
     for (int q = tid; q < N; q += blockDim.x) sw[q] = L.w[q];
-    __syncthreads();
-    const bool active = tid < N3;
+    load_faces<N>(L, col, iz, tid, sface, sown);
+    // node role
+    const bool nact = tid < N3;
     const int i = tid % N, j = (tid / N) % N, k = tid / N2;
-    R facc[3] = {0, 0, 0};
-    if (active) {
-        const int col = e % L.n_cols, iz = e / L.n_cols;
-        const NodeGeo<R> g = node_geo<N>(L, col, iz, i, j);
-        R G[3][3], S[6], T[6];
+    NodeGeo<R> g = nact ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
+    // face role
+    const bool fact = tid < 6 * N2;
+    const int f = tid / N2, fi = tid % N2;
+    int fi_i = 0, fi_j = 0, fi_k = 0;
+    if (fact) face_node<N>(f, fi, fi_i, fi_j, fi_k);
+    NodeGeo<R> gf = fact ? node_geo<N>(L, col, iz, fi_i, fi_j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
+    const R sig_side = (fact && f < 4) ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : R(0);
+    __syncthreads();
+    g.hz = sown[3];
+    gf.hz = sown[3];
+    // neighbour trace and traction of this face node: in flight during the gradient
+    const FaceInfo<R> fo = sface[fact ? f : 0];
+    R un[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
+    if (fact && fo.bc == 0) {
+        int i2, j2, k2;
+        const Nbr nb{fo.e, fo.f, fo.flip, 0};
+        matching_node<N>(f, nb, fi_i, fi_j, fi_k, i2, j2, k2);
+        const R* up = u + (size_t)fo.e * 3 * N3 + k2 * N2 + j2 * N + i2;
+        const R* tp = tau + ((size_t)fo.e * 6 + fo.f) * 3 * N2 + face_index<N>(fo.f, i2, j2, k2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            un[c] = up[c * N3];
+            tn[c] = tp[c * N2];
+        }
+    }
+    const R c11 = sown[0], c12 = sown[1], c44 = sown[2];
+    // 1. node lanes: unlifted gradient and stress; interior traction on each face slot
+    R S[6];
+    const bool fxi = (i == 0) | (i == N - 1), feta = (j == 0) | (j == N - 1), fzeta = (k == 0) | (k == N - 1);
+    if (nact) {
+        R G[3][3], T[6];
         gradient<N>(su, sD, i, j, k, g, G);
         sym_of(G, S);
-        const int m = L.zmat[iz];
-        const R c11 = L.mat[3 * m], c12 = L.mat[3 * m + 1], c44 = L.mat[3 * m + 2];
-        R Tint[6];
-        cubic_stress(c11, c12, c44, S, Tint);
-        const bool fi = (i == 0) | (i == N - 1), fj = (j == 0) | (j == N - 1), fk = (k == 0) | (k == N - 1);
-        const int faces[3] = {fi ? (i == 0 ? 0 : 1) : -1, fj ? (j == 0 ? 2 : 3) : -1, fk ? (k == 0 ? 4 : 5) : -1};
-        R lift[6] = {0, 0, 0, 0, 0, 0};
+        if (fxi | feta | fzeta) {
+            cubic_stress(c11, c12, c44, S, T);
+            const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
+                                  fzeta ? (k == 0 ? 4 : 5) : -1};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (faces[q] < 0) continue;
+                R n[3], amag, t[3];
+                face_normal(faces[q], g, n, amag);
+                traction(n, T, t);
+                const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
+                sFT[slot] = t[0];
+                sFT[slot + N2] = t[1];
+                sFT[slot + 2 * N2] = t[2];
+            }
+        }
+    }
+    __syncthreads();
+    // 2. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
+    if (fact) {
+        R n[3], amag;
+        face_normal(f, gf, n, amag);
+        R wsig, lr;
+        if (f >= 4) {
+            wsig = sw[fi_i] * sw[fi_j] * gf.det2;
+            lr = R(2) / (sw[fi_k] * gf.hz);
+        } else if (f < 2) {
+            wsig = sw[fi_j] * sw[fi_k] * R(0.5) * gf.hz * gf.det2 * amag;
+            lr = amag / sw[fi_i];
+        } else {
+            wsig = sw[fi_i] * sw[fi_k] * R(0.5) * gf.hz * gf.det2 * amag;
+            lr = amag / sw[fi_j];
+        }
+        const int qn = fi_k * N2 + fi_j * N + fi_i;
+        const int slot = f * 3 * N2 + fi;
+        R jump[3] = {0, 0, 0}, flux[3] = {0, 0, 0};
+        if (fo.bc == 0 || fo.bc == DGTN_BC_DIRICHLET) {
+            const bool interior = fo.bc == 0;
+            const R sigma = (f < 4) ? sig_side : L.penalty_n2 / (interior ? min(gf.hz, fo.hz) : gf.hz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) jump[c] = interior ? su[c * N3 + qn] - un[c] : R(2) * su[c * N3 + qn];
+            R Sj[6], Tj[6], pen[3];
+            sym_outer(n, jump, Sj);
+            cubic_stress(fo.c11, fo.c12, fo.c44, Sj, Tj);
+            traction(n, Tj, pen);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R tint = sFT[slot + c * N2];
+                flux[c] = (interior ? R(0.5) * (tint - tn[c]) : tint) - sigma * pen[c];
+            }
+        }
+        // Neumann faces: no jump and, for homogeneous data, no flux
+        R Sj[6];
+        sym_outer(n, jump, Sj);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) sLF[f * 6 * N2 + s * N2 + fi] = R(-0.5) * lr * Sj[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sFT[slot + c * N2] = -wsig * flux[c];
+    }
+    __syncthreads();
+    // 3. node lanes: lifted strain, stress and the volume fluxes F
+    R Fr[9];
+    if (nact) {
+        const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
+                              fzeta ? (k == 0 ? 4 : 5) : -1};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int f = faces[q];
-            if (f < 0) continue;
-            R n[3], amag;
-            face_normal(f, g, n, amag);
-            // w_face J^Sigma and the lift factor w_face J^Sigma / (w J)
-            R wsig, lr;
-            if (f >= 4) {
-                wsig = sw[i] * sw[j] * g.det2;
-                lr = R(2) / (sw[k] * g.hz);
-            } else if (f < 2) {
-                wsig = sw[j] * sw[k] * R(0.5) * g.hz * g.det2 * amag;
-                lr = amag / sw[i];
-            } else {
-                wsig = sw[i] * sw[k] * R(0.5) * g.hz * g.det2 * amag;
-                lr = amag / sw[j];
-            }
-            R tint[3];
-            traction(n, Tint, tint);
-            const Nbr nb = neighbour(L, col, iz, f);
-            R jump[3] = {0, 0, 0}, flux[3] = {0, 0, 0};
-            const R* uo = su;  // own values at this node
-            const int qn = k * N2 + j * N + i;
-            if (nb.bc == 0) {
-                int i2, j2, k2;
-                matching_node<N>(f, nb, i, j, k, i2, j2, k2);
-                const R* un = u + (size_t)nb.e * 3 * N3 + k2 * N2 + j2 * N + i2;
-                const R* tn = tau + ((size_t)nb.e * 6 + nb.f) * 3 * N2 + face_index<N>(nb.f, i2, j2, k2);
-                const int izn = nb.e / L.n_cols;
-                const int mn = L.zmat[izn];
-                R sigma;
-                if (f < 4) {
-                    const int t = (f < 2) ? j : i;
-                    sigma = L.sig_side[((size_t)col * 4 + f) * N + t];
-                } else {
-                    sigma = L.penalty_n2 / min(g.hz, L.hz[izn]);
-                }
+            if (faces[q] < 0) continue;
+            const int base = faces[q] * 6 * N2 + face_index<N>(faces[q], i, j, k);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) jump[c] = uo[c * N3 + qn] - un[c * N3];
-                R Sj[6], Tj[6], pen[3];
-                sym_outer(n, jump, Sj);
-                cubic_stress(R(0.5) * (c11 + L.mat[3 * mn]), R(0.5) * (c12 + L.mat[3 * mn + 1]),
-                             R(0.5) * (c44 + L.mat[3 * mn + 2]), Sj, Tj);
-                traction(n, Tj, pen);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) flux[c] = R(0.5) * (tint[c] - tn[c * N2]) - sigma * pen[c];
-            } else if (nb.bc == DGTN_BC_DIRICHLET) {
-                R sigma;
-                if (f < 4) {
-                    const int t = (f < 2) ? j : i;
-                    sigma = L.sig_side[((size_t)col * 4 + f) * N + t];
-                } else {
-                    sigma = L.penalty_n2 / g.hz;
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) jump[c] = R(2) * uo[c * N3 + qn];
-                R Sj[6], Tj[6], pen[3];
-                sym_outer(n, jump, Sj);
-                cubic_stress(c11, c12, c44, Sj, Tj);
-                traction(n, Tj, pen);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) flux[c] = tint[c] - sigma * pen[c];
-            }
-            // Neumann faces: no jump and, for homogeneous data, no flux
-            R Sj[6];
-            sym_outer(n, jump, Sj);
-#pragma unroll
-            for (int s = 0; s < 6; ++s) lift[s] -= R(0.5) * lr * Sj[s];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) facc[c] -= wsig * flux[c];
+            for (int s = 0; s < 6; ++s) S[s] += sLF[base + s * N2];
         }
-#pragma unroll
-        for (int s = 0; s < 6; ++s) S[s] += lift[s];
+        R T[6];
         cubic_stress(c11, c12, c44, S, T);
         const R wJ = sw[i] * sw[j] * sw[k] * g.det2 * R(0.5) * g.hz;
         const R dz = R(2) / g.hz;
@@ -332,18 +419,37 @@ __global__ __launch_bounds__(threads_for<N>()) void k_apply(LevelView<R> L, cons
         const R Tx[3] = {T[0], T[3], T[4]};
         const R Ty[3] = {T[3], T[1], T[5]};
         const R Tz[3] = {T[4], T[5], T[2]};
-        const int qn = k * N2 + j * N + i;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sF[(0 + c) * N3 + qn] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
-            sF[(3 + c) * N3 + qn] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
-            sF[(6 + c) * N3 + qn] = wJ * dz * Tz[c];
+            Fr[c] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
+            Fr[3 + c] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
+            Fr[6 + c] = wJ * dz * Tz[c];
         }
     }
-    __syncthreads();
-    if (!active) return;
-    R* oe = out + (size_t)e * 3 * N3;
+    __syncthreads();  // every lane is done reading u from LDS
+    R* sF = sbuf;
+    if (nact) {
+        const int qn = k * N2 + j * N + i;
 #pragma unroll
+        for (int s = 0; s < 9; ++s) sF[s * N3 + qn] = Fr[s];
+    }
+    __syncthreads();
+    if (!nact) return;
+    // 4. weak divergence plus the face fluxes
+    R facc[3] = {0, 0, 0};
+    {
+        const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
+                              fzeta ? (k == 0 ? 4 : 5) : -1};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (faces[q] < 0) continue;
+            const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) facc[c] += sFT[slot + c * N2];
+        }
+    }
+    R* oe = out + (size_t)e * 3 * N3;
+#pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         R r = 0;
         const R* Fx = sF + (0 + c) * N3;
@@ -458,7 +564,7 @@ template <typename R>
 hipError_t launch_traction(const LevelView<R>& L, const R* u, R* tau, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -467,7 +573,7 @@ template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }
