@@ -30,6 +30,20 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+
+# The rocprofv3 runs whose output --summarize reads (from the repository root).
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run --output-format csv -- "
+             "python3 bench.py --no-cpu --no-solve --steps 2 --reps 20 --warmup 1",
+    "apply_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/apply_fetch -o run --output-format csv -- "
+                   "python3 bench.py --no-cpu --no-solve --steps 1 --reps 4 --warmup 1",
+    "apply_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/apply_write -o run --output-format csv -- "
+                   "python3 bench.py --no-cpu --no-solve --steps 1 --reps 4 --warmup 1",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copy_fetch -o run --output-format csv -- "
+                  "python3 bench.py --calib-copy",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_write -o run --output-format csv -- "
+                  "python3 bench.py --calib-copy",
+}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -106,6 +120,53 @@ def cpu_baseline(spec, budget_s=15.0):
                       f"(NumPy FP64, single thread), {dt:.2f} s each"}
 
 
+def time_to_u(P, target=1e-8, log=None):
+    """Time-to-U of the FP64- and the FP32-preconditioned solve.
+
+    The reference U is a tight FP64 solve in the same run (the library's FP64
+    energies match the oracle's to 1e-10 on the workloads the oracle can
+    solve).  For each preconditioner precision the loosest stopping tolerance
+    whose U lies within `target` of the reference is found by a sweep, then a
+    solve at that tolerance is timed from the call to the energies on the host
+    (load vector and geometry already resident)."""
+    import torch
+    import paper_2111_06893_amd as dgtn
+
+    def solve(prec, rtol, max_iter=40000):
+        opts = dgtn.default_opts(prec, rtol=rtol, max_iter=max_iter)
+        b = P.rhs()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, st = P.solve(b, opts=opts, raise_on_noconv=False)
+        U = P.energy(u)
+        dt = time.perf_counter() - t0
+        return U, st, dt
+
+    Uref, st, dt = solve(64, 1e-11)
+    if log:
+        log(f"reference solve: {st.iters} iterations, rel.res {st.rel_res:.2e}, {dt:.2f} s")
+    out = {"reference": {"U": float(Uref.sum()), "U_layers": Uref.tolist(), "iters": st.iters,
+                         "rel_res": st.rel_res, "seconds": dt}}
+    for prec in (64, 32):
+        chosen = None
+        for rtol in (1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10):
+            U, st, dt = solve(prec, rtol)
+            err = float(np.max(np.abs(U - Uref) / np.abs(Uref)))
+            if log:
+                log(f"precond fp{prec} rtol {rtol:.0e}: {st.iters} it, {dt:.3f} s, max layer U err {err:.2e}")
+            if err <= target:
+                chosen = rtol
+                break
+        if chosen is None:
+            out[f"fp{prec}_precond"] = None
+            continue
+        U, st, dt = solve(prec, chosen)  # timed at the calibrated tolerance
+        err = float(np.max(np.abs(U - Uref) / np.abs(Uref)))
+        out[f"fp{prec}_precond"] = {"time_to_U_s": dt, "iters": st.iters, "rtol": chosen,
+                                    "U_rel_err": err, "ms_per_iter": dt / max(st.iters, 1) * 1e3}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,7 +178,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (HBM-counter calibration)")
+    ap.add_argument("--summarize", metavar="PROF_DIR",
+                    help="write profiles/ summaries from rocprofv3 output in PROF_DIR and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(args.summarize, PROFILE_COMMANDS)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described, not built.", file=sys.stderr)
@@ -206,9 +272,93 @@ def main():
         "flop_frac_f64": fl / a64 / 1e12 / FP64_PEAK_TFLOPS,
         "flop_frac_f32": fl / a32 / 1e12 / FP32_PEAK_TFLOPS,
     }
+    traffic = measured_traffic()
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
+    if not args.no_solve:
+        out["time_to_U"] = time_to_u(P, log=lambda s: print("[bench] " + s, file=sys.stderr, flush=True))
+        t64 = (out["time_to_U"].get("fp64_precond") or {}).get("time_to_U_s")
+        t32 = (out["time_to_U"].get("fp32_precond") or {}).get("time_to_U_s")
+        if t64 and t32:
+            out["time_to_U"]["speedup_fp32_precond"] = t64 / t32
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def summarize_profiles(prof_dir, commands):
+    """Writes profiles/ summaries from rocprofv3 output under prof_dir:
+    kernel_stats of the kernel trace, and the HBM traffic of k_apply<7,double>
+    from FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a plain
+    256 MiB copy (calib_copy)."""
+    import csv
+    import collections
+
+    def pmc(sub, counter):
+        rows = list(csv.DictReader(open(os.path.join(prof_dir, sub, "run_counter_collection.csv"))))
+        agg = collections.defaultdict(list)
+        for r in rows:
+            if r["Counter_Name"] == counter:
+                agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stats = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "run_kernel_stats.csv"))))
+    lines = ["# Kernel durations, thin-coating cylinder (2000 elements, p = 6, 2,058,000 DoF)", "",
+             "Command (from the repository root, TMPDIR=/tmp):", "", "    " + commands["trace"], "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in stats[:14]:
+        name = r["Name"].split("(")[0].replace("dgtn::(anonymous namespace)::", "")[:70]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} % |")
+    open(os.path.join(out_dir, "kernels_config2_trace.md"), "w").write("\n".join(lines) + "\n")
+
+    copy_bytes = 32 * 2 ** 20 * 8
+    cf = [v for k, vs in pmc("copy_fetch", "FETCH_SIZE").items() if "elementwise" in k for v in vs]
+    cw = [v for k, vs in pmc("copy_write", "WRITE_SIZE").items() if "elementwise" in k for v in vs]
+    # the first elementwise dispatch is the fill (write only); the others are the copies
+    fetch_factor = copy_bytes / (max(cf) * 1024.0)
+    write_factor = copy_bytes / (max(cw) * 1024.0)
+    key = [k for k in pmc("apply_fetch", "FETCH_SIZE") if "k_apply<7, double>" in k][0]
+    f = pmc("apply_fetch", "FETCH_SIZE")[key]
+    w = pmc("apply_write", "WRITE_SIZE")[key]
+    fetch = float(np.mean(f)) * 1024.0 * fetch_factor
+    write = float(np.mean(w)) * 1024.0 * write_factor
+    spec = W.config2()
+    d = {"kernel": "k_apply<7,double>", "workload": "config2 (2000 elements, p=6)",
+         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+         "hbm_bytes_per_launch": fetch + write, "algorithmic_bytes_per_launch": apply_bytes(spec, 8),
+         "fetch_calibration_factor": fetch_factor, "write_calibration_factor": write_factor,
+         "kernels_hip_sha256_16": kernel_source_hash(), "commands": commands}
+    json.dump(d, open(os.path.join(out_dir, "k_apply_config2_traffic.json"), "w"), indent=1)
+    txt = ["# HBM traffic of k_apply<7,double> on the thin-coating cylinder (2,058,000 DoF)", "",
+           f"FETCH_SIZE per launch {np.mean(f):.0f} KiB x {fetch_factor:.3f} = {fetch / 1e6:.2f} MB",
+           f"WRITE_SIZE per launch {np.mean(w):.0f} KiB x {write_factor:.3f} = {write / 1e6:.2f} MB",
+           f"algorithmic bytes per launch {apply_bytes(spec, 8) / 1e6:.2f} MB", "",
+           "Calibration: the same counters on a plain copy of 256 MiB (bench.py --calib-copy) read "
+           f"{max(cf):.0f} KiB fetched and {max(cw):.0f} KiB written per copy.", "", "Commands:", ""]
+    txt += ["    " + c for c in commands.values()]
+    open(os.path.join(out_dir, "k_apply_config2_traffic.md"), "w").write("\n".join(txt) + "\n")
+    print("\n".join(lines + [""] + txt))
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2111_06893_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of k_apply<7,double> from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_apply_config2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return d["hbm_bytes_per_launch"]
 
 
 if __name__ == "__main__":
