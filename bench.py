@@ -309,7 +309,7 @@ def summarize_profiles(prof_dir, commands):
              "Command (from the repository root, TMPDIR=/tmp):", "", "    " + commands["trace"], "",
              "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
     for r in stats[:14]:
-        name = r["Name"].split("(")[0].replace("dgtn::(anonymous namespace)::", "")[:70]
+        name = r["Name"].replace("dgtn::(anonymous namespace)::", "").replace("void ", "").split("(")[0][:70]
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} % |")
     open(os.path.join(out_dir, "kernels_config2_trace.md"), "w").write("\n".join(lines) + "\n")
