@@ -47,7 +47,7 @@ typedef enum {
     DGTN_EINVAL = -1,   /* invalid argument or problem description         */
     DGTN_EMESH = -2,    /* mesh construction failed (non-conforming, det<=0)*/
     DGTN_EHIP = -3,     /* a HIP runtime call failed                       */
-    DGTN_ENOCONV = -4,  /* solver hit its iteration limit                  */
+    DGTN_ENOCONV = -4,  /* solver hit its iteration limit or stagnated     */
     DGTN_ENOMEM = -5,   /* bound workspace too small                       */
     DGTN_ENAN = -6      /* NaN/Inf met in the solver                       */
 } dgtn_status;
@@ -181,8 +181,10 @@ dgtn_status dgtn_apply_stage(dgtn_ctx* ctx, int precision, int stage, const void
 dgtn_status dgtn_rhs(dgtn_ctx* ctx, double* b, hipStream_t stream);
 
 /* Solves A u = b; u holds the initial guess on entry and the solution on
- * exit (device, double).  Returns DGTN_ENOCONV if max_iter is reached
- * (u then holds the last iterate), DGTN_ENAN on a NaN/Inf. */
+ * exit (device, double).  Returns DGTN_ENOCONV if max_iter is reached or
+ * the residual stagnates above rtol (flexible CG losing positive curvature
+ * twice without progress of the true residual: rtol below the attainable
+ * accuracy); u then holds the last iterate.  DGTN_ENAN on a NaN/Inf. */
 dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* b,
                        double* u, dgtn_solve_stats* stats, hipStream_t stream);
 
@@ -199,6 +201,39 @@ dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const 
  * Synchronises the stream. */
 dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers,
                         hipStream_t stream);
+
+/* Parameters of the energy gradient (the derivative of the layer energies of
+ * Sec. 2.1 with respect to the materials of eqs. constrel_iso / constrel_cryst
+ * and the layer thicknesses: the quantity the design exploration proposed in
+ * Sec. 4 needs).  DGTN_PARAM_C11/C12/C44: a cubic
+ * constant of material `index` (any material: an isotropic one has
+ * c11 = lambda + 2 mu, c12 = lambda, c44 = mu); DGTN_PARAM_YOUNGS / POISSON:
+ * Young's modulus / Poisson ratio of isotropic material `index`;
+ * DGTN_PARAM_THICKNESS: thickness of layer `index` (all its element
+ * thicknesses scale with it, the layers below translate). */
+enum { DGTN_PARAM_C11 = 0, DGTN_PARAM_C12 = 1, DGTN_PARAM_C44 = 2, DGTN_PARAM_YOUNGS = 3,
+       DGTN_PARAM_POISSON = 4, DGTN_PARAM_THICKNESS = 5 };
+typedef struct {
+    int kind;
+    int index;
+} dgtn_param;
+
+/* g = dJ/du for J = sum_k w_k U_k (U_k the layer energies of dgtn_energy):
+ * the layer-weighted energy form applied to u, which is the right-hand side of
+ * the adjoint system A lambda = g.  w_layers: host, n_layers weights, or NULL
+ * for all ones.  u, g: device double, n_dof values, not aliased. */
+dgtn_status dgtn_energy_grad(dgtn_ctx* ctx, const double* u, const double* w_layers, double* g,
+                             hipStream_t stream);
+
+/* Adjoint gradient of J = sum_k w_k U_k with respect to n_params parameters:
+ *   dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u,
+ * u the solution of A u = b and lambda that of A lambda = dJ/du (A is
+ * symmetric; the load does not depend on the parameters).  A_theta u and
+ * K_w,theta are evaluated exactly by the operator and energy kernels on dual
+ * numbers.  u, lam: device double; dJ: host, n_params values.  Available for
+ * p <= 5 (DGTN_EINVAL otherwise).  Synchronises the stream. */
+dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const double* w_layers,
+                      int n_params, const dgtn_param* params, double* dJ, hipStream_t stream);
 
 /* Thermal-noise power spectral density from the layer energies:
  * S_x = 4 kB T sum_k phi_k U_k / (pi f F0^2), the reading of eqs.

@@ -15,7 +15,11 @@ import numpy as np
 from . import _lib
 from ._lib import DgtnError, check, load
 
-__all__ = ["Problem", "DgtnError", "noise_psd", "load", "problem_struct", "default_opts"]
+__all__ = ["Problem", "DgtnError", "noise_psd", "load", "problem_struct", "default_opts", "PARAM_KINDS",
+           "with_params", "EnergyFn", "layer_energies"]
+
+# Parameter kinds of the energy gradient (dgtn_param.kind)
+PARAM_KINDS = {"c11": 0, "c12": 1, "c44": 2, "youngs": 3, "poisson": 4, "thickness": 5}
 
 _BC = {"top", "bottom", "side"}
 
@@ -43,6 +47,40 @@ def problem_struct(spec):
         F0=ld["F0"], r0=ld["r0"], xc=ld["xc"], yc=ld["yc"],
         bc_top=bc["top"], bc_bottom=bc["bottom"], bc_side=bc["side"], penalty=spec["penalty"])
     return p, (mats, lays)
+
+
+def _cubic_constants(m):
+    if m["kind"] == "cubic":
+        return {k: m[k] for k in ("c11", "c12", "c44")}
+    Y, nu = m["Y"], m["nu"]
+    lam = Y * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = Y / (2 * (1 + nu))
+    return {"c11": lam + 2 * mu, "c12": lam, "c44": mu}
+
+
+def with_params(spec, params, values):
+    """Copy of spec with the parameters [(kind, index)] set to values.  Setting
+    a cubic constant of an isotropic material turns it into the equivalent
+    cubic material first."""
+    import copy
+    s = copy.deepcopy(spec)
+    for (kind, index), v in zip(params, values):
+        v = float(v)
+        if kind == "thickness":
+            s["layers"][index]["thickness"] = v
+            continue
+        m = s["materials"][index]
+        if kind in ("c11", "c12", "c44"):
+            if m["kind"] != "cubic":
+                m = s["materials"][index] = {"kind": "cubic", **_cubic_constants(m)}
+            m[kind] = v
+        elif kind in ("youngs", "poisson"):
+            if m["kind"] != "iso":
+                raise ValueError(f"material {index} is not isotropic")
+            m["Y" if kind == "youngs" else "nu"] = v
+        else:
+            raise ValueError(f"unknown parameter kind {kind!r}")
+    return s
 
 
 def default_opts(precision=64, **kw):
@@ -181,6 +219,43 @@ class Problem:
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
         return out
 
+    def energy_grad(self, u, w_layers=None):
+        """g = dJ/du for J = sum_k w_k U_k (device float64, the adjoint right-hand side)."""
+        import torch
+        self._ensure()
+        self._check_field(u, torch.float64)
+        g = torch.empty_like(u)
+        w = self._weights(w_layers)
+        check(self.lib.dgtn_energy_grad(self.ctx, ctypes.c_void_p(u.data_ptr()),
+                                        w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.c_void_p(g.data_ptr()), self._stream()))
+        return g
+
+    def grad(self, u, lam, params, w_layers=None):
+        """dJ/dtheta (numpy) for params = [(kind, index)], given the solution u
+        and the adjoint solution lam of A lam = energy_grad(u, w_layers)."""
+        import torch
+        self._ensure()
+        self._check_field(u, torch.float64)
+        self._check_field(lam, torch.float64)
+        arr = (_lib.Param * max(1, len(params)))()
+        for i, (kind, index) in enumerate(params):
+            if kind not in PARAM_KINDS:
+                raise ValueError(f"unknown parameter kind {kind!r}")
+            arr[i] = _lib.Param(PARAM_KINDS[kind], index)
+        w = self._weights(w_layers)
+        out = np.zeros(max(1, len(params)))
+        check(self.lib.dgtn_grad(self.ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(params), arr,
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
+        return out[:len(params)]
+
+    def _weights(self, w_layers):
+        w = np.ones(self.n_layers) if w_layers is None else np.ascontiguousarray(w_layers, dtype=np.float64)
+        if w.shape != (self.n_layers,):
+            raise ValueError(f"expected {self.n_layers} layer weights")
+        return w
+
     def solve(self, b=None, u0=None, opts=None, raise_on_noconv=True):
         """Solves A u = b (b defaults to the load vector); returns (u, stats)."""
         import torch
@@ -242,3 +317,51 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def _energy_fn():
+    import torch
+
+    class EnergyFn(torch.autograd.Function):
+        """theta -> per-layer elastic energies U_k (float64, on the host).
+
+        forward(theta, spec, params, opts): theta holds the values of
+        params = [(kind, index)] (see PARAM_KINDS) substituted into spec; the
+        problem is solved on the current device.  backward: with the incoming
+        gradient as layer weights w, one adjoint solve A lam = dJ/du and the
+        parameter derivatives of dgtn_grad give w . dU/dtheta.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, spec, params, opts=None):
+            params = [tuple(p) for p in params]
+            prob = Problem(with_params(spec, params, theta.detach().cpu().tolist()))
+            o = opts if opts is not None else default_opts()
+            u, _ = prob.solve(opts=o)
+            ctx.state = (prob, u, params, o)
+            return torch.as_tensor(prob.energy(u), dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gU):
+            prob, u, params, o = ctx.state
+            w = gU.detach().cpu().to(torch.float64).numpy()
+            lam, _ = prob.solve(b=prob.energy_grad(u, w), opts=o)
+            dJ = prob.grad(u, lam, params, w)
+            return torch.as_tensor(dJ, dtype=torch.float64), None, None, None
+
+    return EnergyFn
+
+
+def __getattr__(name):
+    # torch is imported on first use only, so host-only users of the library need not load it
+    if name == "EnergyFn":
+        fn = _energy_fn()
+        globals()["EnergyFn"] = fn
+        return fn
+    raise AttributeError(name)
+
+
+def layer_energies(theta, spec, params, opts=None):
+    """Differentiable per-layer energies U_k(theta) (see EnergyFn)."""
+    fn = globals().get("EnergyFn") or __getattr__("EnergyFn")
+    return fn.apply(theta, spec, params, opts)

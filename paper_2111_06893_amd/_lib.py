@@ -41,6 +41,10 @@ class SolveOpts(ctypes.Structure):
                 ("smoother", c_int), ("krylov", c_int)]
 
 
+class Param(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("index", c_int)]
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", c_int), ("restarts", c_int), ("rel_res", c_double), ("t_solve_s", c_double)]
 
@@ -57,6 +61,8 @@ _SIGS = {
     "dgtn_solve": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, P(SolveStats), c_void_p]),
     "dgtn_precondition": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, c_void_p]),
     "dgtn_energy": (c_int, [c_void_p, c_void_p, P(c_double), c_void_p]),
+    "dgtn_energy_grad": (c_int, [c_void_p, c_void_p, P(c_double), c_void_p, c_void_p]),
+    "dgtn_grad": (c_int, [c_void_p, c_void_p, c_void_p, P(c_double), c_int, P(Param), P(c_double), c_void_p]),
     "dgtn_noise_psd": (c_int, [P(c_double), P(c_double), c_int, c_double, c_double, c_double, P(c_double)]),
     "dgtn_node_coords": (c_int, [c_void_p, P(c_double)]),
     "dgtn_level_info": (c_int, [c_void_p, P(SolveOpts), c_int, P(c_int), P(c_int), P(c_int)]),

@@ -79,6 +79,7 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
         L.off_xy = lay.take(8 * (size_t)L.n_cols * 2 * N2);
     }
     c->off_Ue = lay.take(8 * (size_t)c->levels[0].E);
+    plan_adjoint(c, lay);
     plan_solver(c, opts, lay);
 }
 
@@ -262,6 +263,8 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
             HIP_CHECK(puti(L.off_zmat, L.zmat));
             HIP_CHECK(put64(L.off_xy, L.xy));
         }
+        st = bind_adjoint(c, s);
+        if (st != DGTN_OK) return st;
         st = bind_solver(c, s);
         if (st != DGTN_OK) return st;
         HIP_CHECK(hipStreamSynchronize(s));

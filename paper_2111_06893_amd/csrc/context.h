@@ -5,9 +5,18 @@
 
 #include <vector>
 
+#include "dual.h"
 #include "internal.h"
 
 namespace dgtn {
+
+// Workspace offsets of the adjoint's dual-number copies of the finest level.
+struct AdjointLayout {
+    bool ok = false;  // allocated (the dual kernels cover N <= 6)
+    size_t wz = 0, u = 0, Au = 0, tau = 0, geo2 = 0, sig = 0, hz = 0, mat = 0, D = 0, w = 0, Ue = 0;
+    size_t partial = 0, dots = 0;
+    int nblk = 0;
+};
 
 struct Layout {
     size_t cursor = 0;
@@ -29,6 +38,7 @@ struct dgtn_ctx {
     dgtn_solve_opts bound_opts{};
     bool has_opts = false;
     size_t off_Ue = 0;
+    dgtn::AdjointLayout adj;
     std::vector<std::vector<char>> staging;  // host staging of FP32 uploads
     dgtn::SolverState* solver = nullptr;
     ~dgtn_ctx();
@@ -47,7 +57,21 @@ template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s);
 hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
                       double* b, hipStream_t s);
-hipError_t launch_energy(const LevelView<double>& L, const double* u, double* Ue, hipStream_t s);
+template <typename R>
+hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s);
+hipError_t launch_energy_grad(const LevelView<double>& L, const double* u, const double* wz, double* g, double scale,
+                              hipStream_t s);
+template <>
+hipError_t launch_traction<Dual>(const LevelView<Dual>& L, const Dual* u, Dual* tau, hipStream_t s);
+template <>
+hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dual* tau, Dual* out, Dual scale,
+                              hipStream_t s);
+template <>
+hipError_t launch_energy<Dual>(const LevelView<Dual>& L, const double* u, Dual* Ue, hipStream_t s);
+
+// adjoint.hip
+void plan_adjoint(dgtn_ctx* c, Layout& lay);
+dgtn_status bind_adjoint(dgtn_ctx* c, hipStream_t s);
 
 // solver.hip
 dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts);

@@ -15,6 +15,7 @@
 
 #include <type_traits>
 
+#include "dual.h"
 #include "internal.h"
 
 namespace dgtn {
@@ -501,38 +502,38 @@ __global__ __launch_bounds__(threads_for<N>()) void k_rhs(LevelView<double> L, c
 }
 
 // Per-element energy 1/2 sum_nodes w J D_(i u_j) Y D_(k u_l), in units of y_ref.
-template <int N>
-__global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<double> L, const double* __restrict__ u,
-                                                            double* __restrict__ Ue) {
+// Arithmetic type R (double, or Dual for its derivative along a parameter).
+template <int N, typename R>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<R> L, const double* __restrict__ u,
+                                                            R* __restrict__ Ue) {
     constexpr int N2 = N * N, N3 = N2 * N, NT = threads_for<N>();
-    __shared__ double su[3 * N3];
-    __shared__ double sD[N2];
-    __shared__ double red[NT];
+    __shared__ R su[3 * N3];
+    __shared__ R sD[N2];
+    __shared__ R red[NT];
     const int e = blockIdx.x;
     const int tid = threadIdx.x;
     const double* ue = u + (size_t)e * 3 * N3;
-    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = R(ue[q]);
     for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
     __syncthreads();
-    double dens = 0;
+    R dens = 0;
     if (tid < N3) {
         const int i = tid % N, j = (tid / N) % N, k = tid / N2;
         const int col = e % L.n_cols, iz = e / L.n_cols;
-        const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
-        double G[3][3], S[6], T[6];
+        const NodeGeo<R> g = node_geo<N>(L, col, iz, i, j);
+        R G[3][3], S[6], T[6];
         gradient<N>(su, sD, i, j, k, g, G);
         sym_of(G, S);
         const int m = L.zmat[iz];
         cubic_stress(L.mat[3 * m], L.mat[3 * m + 1], L.mat[3 * m + 2], S, T);
-        const double sdt = S[0] * T[0] + S[1] * T[1] + S[2] * T[2] +
-                           2.0 * (S[3] * T[3] + S[4] * T[4] + S[5] * T[5]);
-        dens = 0.5 * L.w[i] * L.w[j] * L.w[k] * g.det2 * 0.5 * g.hz * sdt;
+        const R sdt = S[0] * T[0] + S[1] * T[1] + S[2] * T[2] + R(2) * (S[3] * T[3] + S[4] * T[4] + S[5] * T[5]);
+        dens = R(0.25) * L.w[i] * L.w[j] * L.w[k] * g.det2 * g.hz * sdt;
     }
     red[tid] = dens;
     __syncthreads();
     // fixed-order reduction (deterministic): strided sums into 64 slots, then a tree
     if (tid < 64) {
-        double acc = 0;
+        R acc = 0;
         for (int q = tid; q < NT; q += 64) acc += red[q];
         red[tid] = acc;
     }
@@ -542,6 +543,59 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<double> L
         __syncthreads();
     }
     if (tid == 0) Ue[e] = red[0];
+}
+
+// g = scale * w(layer) * sum_m Dhat_m^T [w J (J^-1)^m_i Y^{ijkl} D_(k u_l)]: the
+// derivative with respect to u of the layer-weighted energy sum_k w_k U_k.
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy_grad(LevelView<double> L, const double* __restrict__ u,
+                                                                 const double* __restrict__ wz,
+                                                                 double* __restrict__ gout, double scale) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double sbuf[9 * N3];
+    __shared__ double sD[N2];
+    double* su = sbuf;
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    __syncthreads();
+    const bool act = tid < N3;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
+    double Fr[9];
+    if (act) {
+        const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
+        double G[3][3], S[6], T[6];
+        gradient<N>(su, sD, i, j, k, g, G);
+        sym_of(G, S);
+        const int m = L.zmat[iz];
+        cubic_stress(L.mat[3 * m], L.mat[3 * m + 1], L.mat[3 * m + 2], S, T);
+        const double wJ = L.w[i] * L.w[j] * L.w[k] * g.det2 * 0.5 * g.hz;
+        const double dz = 2.0 / g.hz;
+        const double Tx[3] = {T[0], T[3], T[4]}, Ty[3] = {T[3], T[1], T[5]}, Tz[3] = {T[4], T[5], T[2]};
+        for (int c = 0; c < 3; ++c) {
+            Fr[c] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
+            Fr[3 + c] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
+            Fr[6 + c] = wJ * dz * Tz[c];
+        }
+    }
+    __syncthreads();
+    if (act)
+        for (int s = 0; s < 9; ++s) sbuf[s * N3 + tid] = Fr[s];
+    __syncthreads();
+    if (!act) return;
+    const double wl = wz[iz] * scale;
+    for (int c = 0; c < 3; ++c) {
+        double r = 0;
+        for (int a = 0; a < N; ++a) {
+            r += sD[a * N + i] * sbuf[(0 + c) * N3 + k * N2 + j * N + a];
+            r += sD[a * N + j] * sbuf[(3 + c) * N3 + k * N2 + a * N + i];
+            r += sD[a * N + k] * sbuf[(6 + c) * N3 + a * N2 + j * N + i];
+        }
+        gout[(size_t)e * 3 * N3 + c * N3 + tid] = wl * r;
+    }
 }
 
 }  // namespace
@@ -587,14 +641,67 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
     });
 }
 
-hipError_t launch_energy(const LevelView<double>& L, const double* u, double* Ue, hipStream_t s) {
+template <typename R>
+hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_energy<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
+        hipLaunchKernelGGL((k_energy<NN, R>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
         return hipGetLastError();
     });
 }
 
+hipError_t launch_energy_grad(const LevelView<double>& L, const double* u, const double* wz, double* g, double scale,
+                              hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy_grad<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, wz, g, scale);
+        return hipGetLastError();
+    });
+}
+
+// The dual-number operator is used for parameter derivatives at p <= 5 (its
+// LDS footprint doubles); larger N return hipErrorInvalidValue.
+template <typename F>
+hipError_t dispatch_dual(int N, F&& f) {
+    switch (N) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <>
+hipError_t launch_traction<Dual>(const LevelView<Dual>& L, const Dual* u, Dual* tau, hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_traction<NN, Dual>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau);
+        return hipGetLastError();
+    });
+}
+
+template <>
+hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dual* tau, Dual* out, Dual scale,
+                              hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau, out, scale);
+        return hipGetLastError();
+    });
+}
+
+template <>
+hipError_t launch_energy<Dual>(const LevelView<Dual>& L, const double* u, Dual* Ue, hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy<NN, Dual>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
+        return hipGetLastError();
+    });
+}
+
+template hipError_t launch_energy<double>(const LevelView<double>&, const double*, double*, hipStream_t);
 template hipError_t launch_traction<double>(const LevelView<double>&, const double*, double*, hipStream_t);
 template hipError_t launch_traction<float>(const LevelView<float>&, const float*, float*, hipStream_t);
 template hipError_t launch_apply<double>(const LevelView<double>&, const double*, const double*, double*, double,

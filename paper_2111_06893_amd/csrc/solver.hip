@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
+#include <limits>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -931,6 +932,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     int iters = 0, restarts = 0;
     const double target = opts->rtol * (bnorm > 0 ? bnorm : 1.0);
     dgtn_status result = DGTN_OK;
+    std::string why = "iteration limit reached";
     if (opts->krylov == DGTN_KRYLOV_FCG) {
         // flexible preconditioned conjugate gradients (Polak-Ribiere beta), with
         // the FP64 true residual recomputed every `refresh` iterations
@@ -950,6 +952,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         SHIP(hipMemcpyAsync(&rz, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
         SHIP(hipStreamSynchronize(s));
         std::swap(zn, zo);
+        double breakdown_beta = std::numeric_limits<double>::infinity();
         while (beta > target) {
             if (iters >= opts->max_iter) { result = DGTN_ENOCONV; break; }
             if (!std::isfinite(beta) || !std::isfinite(rz)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
@@ -959,10 +962,28 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
             double pq;
             SHIP(hipMemcpyAsync(&pq, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
             SHIP(hipStreamSynchronize(s));
-            if (!(pq > 0) || !std::isfinite(pq)) {
-                if (pq == 0) break;
-                set_error("indefinite operator or preconditioner (p.Ap <= 0)");
-                return DGTN_ENAN;
+            if (!std::isfinite(pq)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
+            if (!(pq > 0)) {
+                // loss of positive curvature: rounding at the attainable accuracy, or a
+                // search direction gone stale.  Restart from the FP64 true residual once
+                // per improvement of it; otherwise report stagnation.
+                if ((st = true_residual(beta)) != DGTN_OK) return st;
+                if (beta <= target) break;
+                if (!(beta < breakdown_beta)) {
+                    why = "stagnated (p.Ap <= 0) at relative residual " + std::to_string(beta / bnorm);
+                    result = DGTN_ENOCONV;
+                    break;
+                }
+                breakdown_beta = beta;
+                ++restarts;
+                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
+                SHIP(vec_cast<double, double>(zn, pp, n, 1.0, s));
+                dx[0] = pr; dy[0] = zn;
+                SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
+                SHIP(hipMemcpyAsync(&rz, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
+                SHIP(hipStreamSynchronize(s));
+                std::swap(zn, zo);
+                continue;
             }
             const double alpha = rz / pq;
             SHIP(vec_axpy(u, alpha, pp, n, s));
@@ -1069,6 +1090,6 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         stats->rel_res = bnorm > 0 ? beta / bnorm : beta;
         stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (result == DGTN_ENOCONV) set_error("iteration limit reached");
+    if (result == DGTN_ENOCONV) set_error(why);
     return result;
 }
