@@ -489,12 +489,46 @@ __global__ __launch_bounds__(kDotThreads) void k_multidot(const double* __restri
     }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > nv) return;
+// out[v] = sum_b partial[v][b]: one workgroup per vector, strided loads then a
+// tree in LDS (fixed order, so the result is deterministic).
+__global__ __launch_bounds__(kDotThreads) void k_reduce_partials(const double* __restrict__ partial, int nblk,
+                                                                 double* __restrict__ out) {
+    __shared__ double red[kDotThreads];
+    const int v = blockIdx.x, tid = threadIdx.x;
     double acc = 0;
-    for (int b = 0; b < nblk; ++b) acc += partial[(size_t)v * nblk + b];
-    out[v] = acc;
+    for (int b = tid; b < nblk; b += kDotThreads) acc += partial[(size_t)v * nblk + b];
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = kDotThreads / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) out[v] = red[0];
+}
+
+// Flexible-CG steps with the scalars kept on the device (no host round trip):
+// sc[0] = p.Ap, sc[1] = breakdown flag; cur[0] = r.z of this iteration.
+// u += alpha p, r -= alpha Ap with alpha = cur[0] / sc[0]; a non-positive p.Ap
+// skips the update and raises the flag for the host to act on.
+__global__ void k_fcg_update(double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
+                             const double* __restrict__ q, const double* __restrict__ cur,
+                             double* __restrict__ sc, size_t n) {
+    const double pq = sc[0];
+    const bool ok = pq > 0;
+    const double alpha = ok ? cur[0] / pq : 0.0;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!ok && t == 0) sc[1] = 1.0;
+    if (t >= n) return;
+    u[t] += alpha * p[t];
+    r[t] -= alpha * q[t];
+}
+
+// p = z + beta p, beta = (nxt[0] - nxt[1]) / cur[0]  (Polak-Ribiere)
+__global__ void k_fcg_direction(double* __restrict__ p, const double* __restrict__ z,
+                                const double* __restrict__ cur, const double* __restrict__ nxt, size_t n) {
+    const double beta = (nxt[0] - nxt[1]) / cur[0];
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = z[t] + beta * p[t];
 }
 
 // w += sum_v coef[v] V_v   (coef on the device)
@@ -667,7 +701,19 @@ hipError_t vec_resid(const R* b, R* y, size_t n, hipStream_t s) {
 hipError_t vec_multidot(const double* V, size_t ldv, int nv, const double* w, size_t n, double* partial, int nblk,
                         double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, nv, w, n, partial, nblk);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(nv + 1, 64)), dim3(64), 0, s, partial, nblk, nv, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv + 1), dim3(kDotThreads), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t fcg_update(double* u, double* r, const double* p, const double* q, const double* cur, double* sc,
+                      size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, r, p, q, cur, sc, n);
+    return hipGetLastError();
+}
+
+hipError_t fcg_direction(double* p, const double* z, const double* cur, const double* nxt, size_t n,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_direction, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, z, cur, nxt, n);
     return hipGetLastError();
 }
 
@@ -696,7 +742,7 @@ hipError_t vec_dotpairs(int np, const double* const* x, const double* const* y, 
         d.y[v] = y[v];
     }
     hipLaunchKernelGGL(k_dotpairs, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partial, nblk, np - 1, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(np), dim3(kDotThreads), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
 

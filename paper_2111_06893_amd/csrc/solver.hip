@@ -60,8 +60,13 @@ struct SolverState {
     int n_coarse = 0;
     size_t off_Ainv[2] = {0, 0}, off_col = 0;
     int m = 0, nblk = 0;
-    size_t off_V = 0, off_Z = 0, off_w = 0, off_r = 0, off_partial = 0, off_dots = 0, off_coef = 0;
+    size_t off_V = 0, off_Z = 0, off_w = 0, off_r = 0, off_partial = 0, off_dots = 0, off_coef = 0, off_sc = 0;
     bool planned = false;
+    // pinned host slots and events for reading solver monitors without stalling the stream
+    double* host_mon = nullptr;
+    hipEvent_t mon_event[2] = {nullptr, nullptr};
+    dgtn_status host_monitor();
+    ~SolverState();
 };
 
 namespace {
@@ -620,6 +625,7 @@ void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
     S.off_partial = lay.take(8 * (size_t)(S.m + 2) * S.nblk);
     S.off_dots = lay.take(8 * (size_t)(S.m + 2));
     S.off_coef = lay.take(8 * (size_t)(S.m + 2));
+    S.off_sc = lay.take(8 * 16);
     S.planned = true;
 }
 
@@ -828,6 +834,28 @@ dgtn_status axpys(dgtn_ctx* c, double* w, const double* V, int nv, const std::ve
 
 }  // namespace dgtn
 
+dgtn_status dgtn::SolverState::host_monitor() {
+    if (host_mon) return DGTN_OK;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        set_error("pinned host allocation for the solver monitors failed");
+        return DGTN_ENOMEM;
+    }
+    host_mon = static_cast<double*>(h);
+    for (auto& e : mon_event)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            set_error("hipEventCreate failed");
+            return DGTN_EHIP;
+        }
+    return DGTN_OK;
+}
+
+dgtn::SolverState::~SolverState() {
+    for (auto& e : mon_event)
+        if (e) (void)hipEventDestroy(e);
+    if (host_mon) (void)hipHostFree(host_mon);
+}
+
 dgtn_ctx::~dgtn_ctx() { delete solver; }
 
 using namespace dgtn;
@@ -933,90 +961,94 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     const double target = opts->rtol * (bnorm > 0 ? bnorm : 1.0);
     dgtn_status result = DGTN_OK;
     std::string why = "iteration limit reached";
-    if (opts->krylov == DGTN_KRYLOV_FCG) {
-        // flexible preconditioned conjugate gradients (Polak-Ribiere beta), with
-        // the FP64 true residual recomputed every `refresh` iterations
-        double* pr = r;                    // residual (true residual above)
+    if (opts->krylov == DGTN_KRYLOV_FCG && beta > target) {
+        // Flexible preconditioned conjugate gradients (Polak-Ribiere beta).  The
+        // scalars stay on the device; the host reads the residual norm and the
+        // breakdown flag of iteration k while iteration k+1 is already queued, so
+        // the GPU never waits for the host.  The FP64 true residual replaces the
+        // recurrence every `refresh` iterations and confirms convergence.
+        double* pr = r;                    // residual
         double* zn = V;                    // z_{k+1}
         double* zo = V + n;                // z_k
         double* pp = V + 2 * n;            // search direction
         double* q = w;                     // A p
+        double* sc = at<double>(c, S.off_sc);  // [0] p.Ap, [1] breakdown flag, [4 + 4s ..] r.z slots
         const int refresh = 50;
-        if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
-        SHIP(vec_cast<double, double>(zn, pp, n, 1.0, s));
+        if ((st = S.host_monitor()) != DGTN_OK) return st;
+        auto slot = [&](int k) { return sc + 4 + 4 * (k & 1); };
+        int par = 0;
         const double* dx[4];
         const double* dy[4];
-        dx[0] = pr; dy[0] = zn;
-        SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
-        double rz;
-        SHIP(hipMemcpyAsync(&rz, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
-        SHIP(hipStreamSynchronize(s));
-        std::swap(zn, zo);
+        // (re)start from the residual in pr: z = M r, p = z, slot(par)[0] = r.z
+        auto start = [&]() -> dgtn_status {
+            dgtn_status e = precondition(c, opts->precond_precision, vo, pr, zn, s);
+            if (e != DGTN_OK) return e;
+            SHIP(vec_cast<double, double>(zn, pp, n, 1.0, s));
+            dx[0] = pr; dy[0] = zn;
+            SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, slot(par), s));
+            SHIP(hipMemsetAsync(sc + 1, 0, sizeof(double), s));
+            std::swap(zn, zo);
+            return DGTN_OK;
+        };
+        if ((st = start()) != DGTN_OK) return st;
         double breakdown_beta = std::numeric_limits<double>::infinity();
-        while (beta > target) {
+        bool have_prev = false;
+        int mon_slot[2] = {0, 0};
+        while (true) {
             if (iters >= opts->max_iter) { result = DGTN_ENOCONV; break; }
-            if (!std::isfinite(beta) || !std::isfinite(rz)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
+            double* cur = slot(par);
+            double* nxt = slot(par + 1);
             if ((st = level_apply<double>(c, 0, pp, q, yr, s)) != DGTN_OK) return st;
             dx[0] = pp; dy[0] = q;
-            SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
-            double pq;
-            SHIP(hipMemcpyAsync(&pq, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
-            SHIP(hipStreamSynchronize(s));
-            if (!std::isfinite(pq)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
-            if (!(pq > 0)) {
-                // loss of positive curvature: rounding at the attainable accuracy, or a
-                // search direction gone stale.  Restart from the FP64 true residual once
-                // per improvement of it; otherwise report stagnation.
-                if ((st = true_residual(beta)) != DGTN_OK) return st;
-                if (beta <= target) break;
-                if (!(beta < breakdown_beta)) {
-                    why = "stagnated (p.Ap <= 0) at relative residual " + std::to_string(beta / bnorm);
-                    result = DGTN_ENOCONV;
-                    break;
-                }
-                breakdown_beta = beta;
-                ++restarts;
-                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
-                SHIP(vec_cast<double, double>(zn, pp, n, 1.0, s));
-                dx[0] = pr; dy[0] = zn;
-                SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
-                SHIP(hipMemcpyAsync(&rz, at<double>(c, S.off_dots), 8, hipMemcpyDeviceToHost, s));
-                SHIP(hipStreamSynchronize(s));
-                std::swap(zn, zo);
-                continue;
-            }
-            const double alpha = rz / pq;
-            SHIP(vec_axpy(u, alpha, pp, n, s));
-            SHIP(vec_axpy(pr, -alpha, q, n, s));
-            ++iters;
-            if (iters % refresh == 0) {
-                if ((st = true_residual(beta)) != DGTN_OK) return st;
+            SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, sc, s));
+            SHIP(fcg_update(u, pr, pp, q, cur, sc, n, s));
+            const int it = iters++;
+            if (iters % refresh == 0) {  // residual replacement
+                if ((st = level_apply<double>(c, 0, u, pr, yr, s)) != DGTN_OK) return st;
+                SHIP(vec_resid<double>(b, pr, n, s));
                 ++restarts;
             }
             if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
             dx[0] = pr; dy[0] = zn;
             dx[1] = pr; dy[1] = zo;
             dx[2] = pr; dy[2] = pr;
-            SHIP(vec_dotpairs(3, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
-            double dd[3];
-            SHIP(hipMemcpyAsync(dd, at<double>(c, S.off_dots), 24, hipMemcpyDeviceToHost, s));
-            SHIP(hipStreamSynchronize(s));
-            beta = std::sqrt(dd[2]);
-            if (verbose && iters % 10 == 0) std::fprintf(stderr, "dgtn fcg it %d rel %.3e\n", iters, beta / bnorm);
-            if (beta <= target) {  // confirm with the FP64 true residual
-                if ((st = true_residual(beta)) != DGTN_OK) return st;
-                if (beta <= target) break;
-                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
-                dx[0] = pr; dy[0] = zn;
-                dx[1] = pr; dy[1] = zo;
-                SHIP(vec_dotpairs(2, dx, dy, n, at<double>(c, S.off_partial), S.nblk, at<double>(c, S.off_dots), s));
-                SHIP(hipMemcpyAsync(dd, at<double>(c, S.off_dots), 16, hipMemcpyDeviceToHost, s));
-                SHIP(hipStreamSynchronize(s));
-            }
-            const double bet = (dd[0] - dd[1]) / rz;
-            rz = dd[0];
-            SHIP(vec_xpby(pp, zn, bet, n, s));
+            SHIP(vec_dotpairs(3, dx, dy, n, at<double>(c, S.off_partial), S.nblk, nxt, s));
+            SHIP(fcg_direction(pp, zn, cur, nxt, n, s));
             std::swap(zn, zo);
+            par ^= 1;
+            // post this iteration's monitors, then read the previous iteration's
+            double* hm = S.host_mon + 16 * (it & 1);
+            mon_slot[it & 1] = par;  // slot(par) now holds this iteration's r.z, r.z_old, r.r
+            SHIP(hipMemcpyAsync(hm, sc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+            SHIP(hipEventRecord(S.mon_event[it & 1], s));
+            if (!have_prev) { have_prev = true; continue; }
+            const int pj = (it - 1) & 1;
+            SHIP(hipEventSynchronize(S.mon_event[pj]));
+            const double* pm = S.host_mon + 16 * pj;
+            const double rr = pm[4 + 4 * (mon_slot[pj] & 1) + 2];
+            const bool broke = pm[1] != 0.0;
+            if (!std::isfinite(rr)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
+            beta = std::sqrt(std::max(rr, 0.0));
+            if (verbose && it % 10 == 0) std::fprintf(stderr, "dgtn fcg it %d rel %.3e\n", it, beta / bnorm);
+            if (!broke && beta > target) continue;
+            // converged by the recurrence, or lost positive curvature: decide on the
+            // FP64 true residual of the current iterate
+            SHIP(hipStreamSynchronize(s));
+            if ((st = true_residual(beta)) != DGTN_OK) return st;
+            if (beta <= target) break;
+            if (broke) {
+                // rounding at the attainable accuracy, or a stale direction: restart
+                // once per improvement of the true residual, else report stagnation
+                if (!(beta < breakdown_beta)) {
+                    why = "stagnated (p.Ap <= 0) at relative residual " + std::to_string(beta / bnorm);
+                    result = DGTN_ENOCONV;
+                    break;
+                }
+                breakdown_beta = beta;
+            }
+            ++restarts;
+            if ((st = start()) != DGTN_OK) return st;
+            have_prev = false;
         }
     }
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
