@@ -105,11 +105,15 @@ typedef struct {
     double y_ref;             /* modulus scale of the internal arithmetic (Pa) */
 } dgtn_info;
 
-/* Krylov solve (Sec. 2.3): restarted flexible GMRES in FP64 on A u = b,
- * preconditioned by a multigrid V-cycle whose levels run in
- * precond_precision (64 or 32 bit); every restart recomputes the FP64 true
- * residual (iterative refinement when the preconditioner is FP32).
- * mg_levels = 1 uses the smoother alone, 0 no preconditioner. */
+/* Krylov solve (Sec. 2.3): flexible CG or restarted flexible GMRES in FP64
+ * on A u = b, preconditioned by a multigrid V-cycle whose levels run in
+ * precond_precision (64 or 32 bit); the FP64 true residual is recomputed
+ * periodically and at convergence (iterative refinement when the
+ * preconditioner is FP32).  mg_levels = 1 uses the additive-Schwarz smoother
+ * alone, 0 no preconditioner.  The paper's Schwarz subdomains overlap; with
+ * column subdomains, overlap = k > 0 extends every column by k node lines into
+ * each horizontal neighbour (and the k x k corner blocks of the diagonal
+ * neighbours), k < N on every level (clamped). */
 typedef struct {
     int precond_precision;    /* 64 or 32                                      */
     int restart;              /* FGMRES restart length m (1..200)              */
@@ -120,6 +124,7 @@ typedef struct {
     double smooth_damping;    /* damping of the additive Schwarz smoother      */
     int smoother;             /* Schwarz subdomains: DGTN_SMOOTH_ELEMENT or DGTN_SMOOTH_COLUMN */
     int krylov;               /* DGTN_KRYLOV_FGMRES or DGTN_KRYLOV_FCG          */
+    int overlap;              /* column-subdomain overlap in node lines (0..3)  */
 } dgtn_solve_opts;
 
 /* Additive-Schwarz subdomains: one element, or one whole z-column of elements
@@ -254,6 +259,14 @@ dgtn_status dgtn_level_info(dgtn_ctx* ctx, const dgtn_solve_opts* opts, int leve
                             int* n_elem, int* n_cols);
 dgtn_status dgtn_smoother_block(dgtn_ctx* ctx, const dgtn_solve_opts* opts, int level, int elem,
                                 double* out);
+
+/* Overlapping column patches of level l (host only): *P = N + 2k (N without
+ * overlap) and, if table is non-NULL, n_cols * P * P ints: for column c and
+ * patch position (a, b) (a along the column's xi, b along eta, own nodes at
+ * k..k+N-1), the node c' * N^2 + j' * N + i' of the 2D column grid it reads,
+ * or -1 (outside the domain, or the corner at a vertex not shared by four
+ * columns). */
+dgtn_status dgtn_patch_table(dgtn_ctx* ctx, const dgtn_solve_opts* opts, int level, int* P, int* table);
 
 /* Node coordinates (host, double, [E][3][N^3]) of the library's mesh. */
 dgtn_status dgtn_node_coords(const dgtn_ctx* ctx, double* xyz);

@@ -85,7 +85,7 @@ def with_params(spec, params, values):
 
 def default_opts(precision=64, **kw):
     o = dict(precond_precision=precision, restart=30, max_iter=20000, rtol=1e-11,
-             mg_levels=1, smooth_steps=1, smooth_damping=1.0, smoother=1, krylov=1)
+             mg_levels=1, smooth_steps=1, smooth_damping=1.0, smoother=1, krylov=1, overlap=1)
     o.update(kw)
     return _lib.SolveOpts(**o)
 
@@ -302,6 +302,17 @@ class Problem:
                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         out = out.reshape(3, 3, N * N + N)
         return out[:, :, :N * N].reshape(3, 3, N, N), out[:, :, N * N:]
+
+    def patch_table(self, opts, level=0):
+        """Gather table of the overlapping column patches: array [n_cols, P, P]
+        of 2D-grid nodes col * N^2 + j * N + i (or -1), indexed [col, b, a]."""
+        Pw = ctypes.c_int()
+        check(self.lib.dgtn_patch_table(self.ctx, ctypes.byref(opts), level, ctypes.byref(Pw), None))
+        _, _, n_cols = self.level_info(opts, level)
+        tab = np.zeros(n_cols * Pw.value ** 2, dtype=np.int32)
+        check(self.lib.dgtn_patch_table(self.ctx, ctypes.byref(opts), level, ctypes.byref(Pw),
+                                        tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return tab.reshape(n_cols, Pw.value, Pw.value)
 
     def noise(self, U_layers, phi, T, f):
         return noise_psd(U_layers, phi, T, f, self.spec["load"]["F0"])

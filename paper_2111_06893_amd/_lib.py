@@ -38,7 +38,7 @@ class Info(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precond_precision", c_int), ("restart", c_int), ("max_iter", c_int), ("rtol", c_double),
                 ("mg_levels", c_int), ("smooth_steps", c_int), ("smooth_damping", c_double),
-                ("smoother", c_int), ("krylov", c_int)]
+                ("smoother", c_int), ("krylov", c_int), ("overlap", c_int)]
 
 
 class Param(ctypes.Structure):
@@ -67,6 +67,7 @@ _SIGS = {
     "dgtn_node_coords": (c_int, [c_void_p, P(c_double)]),
     "dgtn_level_info": (c_int, [c_void_p, P(SolveOpts), c_int, P(c_int), P(c_int), P(c_int)]),
     "dgtn_smoother_block": (c_int, [c_void_p, P(SolveOpts), c_int, c_int, P(c_double)]),
+    "dgtn_patch_table": (c_int, [c_void_p, P(SolveOpts), c_int, P(c_int), P(c_int)]),
     "dgtn_destroy": (None, [c_void_p]),
     "dgtn_last_error": (ctypes.c_char_p, []),
 }

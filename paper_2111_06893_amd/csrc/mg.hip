@@ -202,6 +202,119 @@ __global__ __launch_bounds__(nthreads<N>()) void k_col_bwd(int n_cols, int nzN, 
     }
 }
 
+// ---- overlapping column patches ---------------------------------------------------
+// A column's subdomain is its own N x N node grid extended by k node lines into
+// every horizontal neighbour (and k x k corners of the diagonal neighbours):
+// a P x P patch, P = N + 2k, in the column's own (xi, eta) orientation.
+// pg[col][b * P + a] names the node feeding patch position (a, b) as
+// src_col * N^2 + j * N + i, or -1 where the patch has no node (outside the
+// domain, or a corner at a vertex that is not shared by four columns).
+
+// Gather of r = b - Ax (or b) onto the patches and forward x/y transform:
+// T[c][iz*N + k][col*P2 + b'*P + a'] = sum_{a,b} Sx[a][a'] Sy[b][b'] r_patch[c][k][b][a].
+template <int N, typename R>
+__global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, const int* __restrict__ pg,
+                                                 const R* __restrict__ S, const R* __restrict__ b,
+                                                 const R* __restrict__ Ax, R* __restrict__ T) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    extern __shared__ char smem[];
+    const int P2 = P * P, NP = 3 * N * P2;
+    R* sr = reinterpret_cast<R*>(smem);
+    R* st = sr + NP;
+    R* sS = st + NP;
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int col = e % n_cols, iz = e / n_cols;
+    for (int q = tid; q < 2 * P2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * P2 + q];
+    for (int q = tid; q < NP; q += blockDim.x) {
+        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2;
+        const int src = pg[(size_t)col * P2 + ab];
+        R v = 0;
+        if (src >= 0) {
+            const size_t o = ((size_t)(iz * n_cols + src / N2) * 3 + c) * N3 + k * N2 + src % N2;
+            v = Ax ? b[o] - Ax[o] : b[o];
+        }
+        sr[q] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < NP; q += blockDim.x) {  // x: st[c][k][b][a'] = sum_a Sx[a][a'] sr[c][k][b][a]
+        const int row = q / P, a2 = q % P;
+        R acc = 0;
+        for (int a = 0; a < P; ++a) acc += sS[a * P + a2] * sr[row * P + a];
+        st[q] = acc;
+    }
+    __syncthreads();
+    const size_t ld = (size_t)n_cols * P2;
+    for (int q = tid; q < NP; q += blockDim.x) {  // y
+        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2, b2 = ab / P, a2 = ab % P;
+        const R* sy = sS + P2;
+        const R* src = st + (size_t)(c * N + k) * P2;
+        R acc = 0;
+        for (int bb = 0; bb < P; ++bb) acc += sy[bb * P + b2] * src[bb * P + a2];
+        T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab] = acc;
+    }
+}
+
+// Backward x/y transform in place: T[..][col*P2 + b*P + a] = sum Sx[a][a'] Sy[b][b'] T[..][b'*P + a'].
+template <int N, typename R>
+__global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, int P, const R* __restrict__ S,
+                                                 R* __restrict__ T) {
+    extern __shared__ char smem[];
+    const int P2 = P * P, NP = 3 * N * P2;
+    R* sr = reinterpret_cast<R*>(smem);
+    R* st = sr + NP;
+    R* sS = st + NP;
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int col = e % n_cols, iz = e / n_cols;
+    const size_t ld = (size_t)n_cols * P2;
+    for (int q = tid; q < 2 * P2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * P2 + q];
+    for (int q = tid; q < NP; q += blockDim.x) {
+        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2;
+        sr[q] = T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab];
+    }
+    __syncthreads();
+    for (int q = tid; q < NP; q += blockDim.x) {  // y: st[c][k][b][a'] = sum_b' Sy[b][b'] sr[c][k][b'][a']
+        const int row = q / P2, ab = q % P2, bb = ab / P, a2 = ab % P;
+        const R* sy = sS + P2;
+        const R* src = sr + (size_t)row * P2;
+        R acc = 0;
+        for (int b2 = 0; b2 < P; ++b2) acc += sy[bb * P + b2] * src[b2 * P + a2];
+        st[q] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < NP; q += blockDim.x) {  // x
+        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2, aa = ab % P;
+        const R* src = st + (size_t)q - aa;
+        R acc = 0;
+        for (int a2 = 0; a2 < P; ++a2) acc += sS[aa * P + a2] * src[a2];
+        T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab] = acc;
+    }
+}
+
+// Additive combination: every node sums the patch values of the (up to four)
+// patches that hold it; ps[col][node][4] = patch_col * P2 + position, or -1.
+template <int N, typename R>
+__global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, const int* __restrict__ ps,
+                                                 const R* __restrict__ T, R* __restrict__ x, R omega,
+                                                 int accumulate) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const size_t tot = (size_t)n_cols * n_z * 3 * N3;
+    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= tot) return;
+    const int node = (int)(o % N2), k = (int)((o / N2) % N), c = (int)((o / N3) % 3);
+    const size_t e = o / (3 * N3);
+    const int col = (int)(e % n_cols), iz = (int)(e / n_cols);
+    const int P2 = P * P, nzN = n_z * N;
+    const R* row = T + ((size_t)c * nzN + iz * N + k) * (size_t)n_cols * P2;
+    const int* tab = ps + ((size_t)col * N2 + node) * 4;
+    R acc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = tab[q];
+        if (t >= 0) acc += row[t];
+    }
+    x[o] = (accumulate ? x[o] : R(0)) + omega * acc;
+}
+
 // Batched (over the 3 components, blockIdx.z) tiled product along z:
 //   trans = 1:  Y[i][m] = (sum_z V[z][i] T[z][m]) / (lz[i] + rx lx_a + ry ly_b)
 //   trans = 0:  T[z][m] =  sum_i V[z][i] Y[i][m]
@@ -635,6 +748,32 @@ hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, c
 }
 
 template <typename R>
+hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const int* ps, const R* S,
+                         const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax, R* x,
+                         R omega, R* T, R* Y, hipStream_t s) {
+    const int E = n_cols * n_z, n = n_z * N, ncol = n_cols * P * P;
+    const size_t shm = sizeof(R) * (size_t)(2 * 3 * N * P * P + 2 * P * P);
+    hipError_t err = dispatch(N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_ovl_fwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, pg, S, b, Ax, T);
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    const dim3 grid((ncol + kTN - 1) / kTN, (n + kTM - 1) / kTM, 3);
+    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, P, 1, V, T, Y, lz, lam, rat);
+    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, P, 0, V, Y, T, lz, lam, rat);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    return dispatch(N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_ovl_bwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, S, T);
+        const size_t tot = (size_t)E * 3 * NN * NN * NN;
+        hipLaunchKernelGGL((k_ovl_sum<NN, R>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, n_cols, n_z, P, ps, T,
+                           x, omega, Ax ? 1 : 0);
+        return hipGetLastError();
+    });
+}
+
+template <typename R>
 hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s) {
     hipLaunchKernelGGL((k_prolong_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, uc, uf);
     return hipGetLastError();
@@ -755,6 +894,9 @@ hipError_t vec_scale_copy(const double* x, double* y, double a, size_t n, hipStr
     template hipError_t mg_smooth<R>(int, int, const R*, const R*, const R*, R*, R, hipStream_t);      \
     template hipError_t mg_col_smooth<R>(int, int, int, const R*, const R*, const R*, const R*,         \
                                          const R*, const R*, const R*, R*, R, R*, R*, hipStream_t);    \
+    template hipError_t mg_ovl_smooth<R>(int, int, int, int, const int*, const int*, const R*, const R*, \
+                                         const R*, const R*, const R*, const R*, const R*, R*, R, R*, R*, \
+                                         hipStream_t);                                                  \
     template hipError_t mg_prolong_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);           \
     template hipError_t mg_restrict_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);          \
     template hipError_t mg_prolong_h<R>(int, int, int, int, const int*, const int*, const R*, const R*, \

@@ -46,10 +46,13 @@ struct MgLevel {
     std::vector<double> fdm;  // [E][3 comps][3 dirs][N*N (S, row = node) + N (kappa * lambda)]
     size_t off_fdm[2] = {0, 0};
     size_t off_b[2] = {0, 0}, off_x[2] = {0, 0}, off_t[2] = {0, 0};
-    // column smoother: S [n_cols][2][N2], lam [n_cols][2][N], rat [n_cols][6], V [3][n][n], lz [3][n]
+    // column smoother: S [n_cols][2][P2], lam [n_cols][2][P], rat [n_cols][6], V [3][n][n], lz [3][n];
+    // P = N, or N + 2k for overlapping patches with gather / sum tables pg, ps
+    int P = 0;
     std::vector<double> cS, clam, crat, cV, clz;
+    std::vector<int> pg, ps;
     size_t off_cS[2] = {0, 0}, off_clam[2] = {0, 0}, off_crat[2] = {0, 0}, off_cV[2] = {0, 0}, off_clz[2] = {0, 0};
-    size_t off_cT[2] = {0, 0}, off_cY[2] = {0, 0};
+    size_t off_cT[2] = {0, 0}, off_cY[2] = {0, 0}, off_pg = 0, off_ps = 0;
 };
 
 struct SolverState {
@@ -420,19 +423,134 @@ std::vector<double> column_1d(const Lgl& g, const std::vector<double>& hz, const
     return K;
 }
 
+// 1D DG operator for a unit modulus along a line of elements of widths h[e],
+// interface penalties sig_if[e] between elements e and e + 1, and end
+// conditions lo / hi (END_NONE or END_DIRICHLET with penalties sig_lo / sig_hi).
+std::vector<double> line_1d(const Lgl& g, const std::vector<double>& h, const std::vector<double>& sig_if, int lo,
+                            double sig_lo, int hi, double sig_hi) {
+    const int N = g.N, ne = (int)h.size(), n = ne * N;
+    std::vector<double> K((size_t)n * n, 0.0), u(n), gr(n), S(n), r(n), jl(ne), jh(ne);
+    for (int col = 0; col < n; ++col) {
+        std::fill(u.begin(), u.end(), 0.0);
+        u[col] = 1.0;
+        for (int e = 0; e < ne; ++e)
+            for (int i = 0; i < N; ++i) {
+                double acc = 0;
+                for (int a = 0; a < N; ++a) acc += g.D[i * N + a] * u[e * N + a];
+                gr[e * N + i] = S[e * N + i] = 2.0 / h[e] * acc;
+            }
+        for (int e = 0; e < ne; ++e) {
+            jl[e] = e > 0 ? u[e * N] - u[(e - 1) * N + N - 1] : (lo == END_DIRICHLET ? 2.0 * u[e * N] : 0.0);
+            jh[e] = e < ne - 1 ? u[e * N + N - 1] - u[(e + 1) * N] : (hi == END_DIRICHLET ? 2.0 * u[e * N + N - 1] : 0.0);
+            S[e * N] += jl[e] / (g.w[0] * h[e]);
+            S[e * N + N - 1] -= jh[e] / (g.w[N - 1] * h[e]);
+        }
+        for (int e = 0; e < ne; ++e) {
+            for (int a = 0; a < N; ++a) {
+                double acc = 0;
+                for (int i = 0; i < N; ++i) acc += g.D[i * N + a] * g.w[i] * S[e * N + i];
+                r[e * N + a] = acc;
+            }
+            if (e > 0) r[e * N] += 0.5 * (gr[e * N] + gr[(e - 1) * N + N - 1]) + sig_if[e - 1] * jl[e];
+            else if (lo == END_DIRICHLET) r[e * N] += gr[e * N] + sig_lo * jl[e];
+            if (e < ne - 1) r[e * N + N - 1] -= 0.5 * (gr[e * N + N - 1] + gr[(e + 1) * N]) - sig_if[e] * jh[e];
+            else if (hi == END_DIRICHLET) r[e * N + N - 1] -= gr[e * N + N - 1] - sig_hi * jh[e];
+        }
+        for (int i = 0; i < n; ++i) K[(size_t)i * n + col] = r[i];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double v = 0.5 * (K[(size_t)i * n + j] + K[(size_t)j * n + i]);
+            K[(size_t)i * n + j] = K[(size_t)j * n + i] = v;
+        }
+    return K;
+}
+
+// Node of the 2D column grid at extended coordinates (x, y) of column col (own
+// nodes 0..N-1), reached by crossing faces: col' * N^2 + y' * N + x', or -1.
+// A corner point is accepted only if crossing the xi face first and the eta
+// face first reach the same node (a vertex shared by four columns).
+int locate_node(const Level& L, int col, int x, int y) {
+    const int N = L.N;
+    auto inside = [&](int v) { return v >= 0 && v < N; };
+    auto walk = [&](int c, int px, int py, int first) {
+        for (int step = 0; step < 3; ++step) {
+            if (inside(px) && inside(py)) return c * N * N + py * N + px;
+            const int axis = (!inside(px) && !inside(py)) ? first : (!inside(px) ? 0 : 1);
+            int f, d, t;
+            if (axis == 0) { f = px < 0 ? 0 : 1; d = px < 0 ? -1 - px : px - N; t = py; }
+            else { f = py < 0 ? 2 : 3; d = py < 0 ? -1 - py : py - N; t = px; }
+            const int nb = L.cnbr[c * 4 + f];
+            if (nb < 0) return -1;
+            const int code = L.cnf[c * 4 + f], f2 = code & 3;
+            const int t2 = (code >> 2) ? N - 1 - t : t;
+            switch (f2) {
+                case 0: px = d; py = t2; break;
+                case 1: px = N - 1 - d; py = t2; break;
+                case 2: px = t2; py = d; break;
+                default: px = t2; py = N - 1 - d; break;
+            }
+            c = nb;
+        }
+        return -1;
+    };
+    const int a = walk(col, x, y, 0);
+    if (inside(x) || inside(y)) return a;
+    const int b = walk(col, x, y, 1);
+    return a == b ? a : -1;
+}
+
+// Generalised eigen-decomposition of the restriction of the line operator K
+// (line nodes `idx`, -1 for positions without a node) with the lumped mass
+// `mass`: S (row = patch node, column = mode, S^T M S = I) and lambda; modes
+// of the absent positions are unit vectors with lambda = 1 (they never see data).
+void patch_fdm(const std::vector<double>& K, int nline, const std::vector<double>& mass, const std::vector<int>& idx,
+               double* S_out, double* lam_out) {
+    const int P = (int)idx.size();
+    std::vector<int> real;
+    for (int a = 0; a < P; ++a)
+        if (idx[a] >= 0) real.push_back(a);
+    const int m = (int)real.size();
+    std::vector<double> A((size_t)m * m), Q, lam, ms(m);
+    for (int i = 0; i < m; ++i) ms[i] = 1.0 / std::sqrt(mass[idx[real[i]]]);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            A[(size_t)i * m + j] = ms[i] * K[(size_t)idx[real[i]] * nline + idx[real[j]]] * ms[j];
+    jacobi_eigen(m, A, Q, lam);
+    double lmax = 0;
+    for (double l : lam) lmax = std::max(lmax, l);
+    for (int q = 0; q < P * P; ++q) S_out[q] = 0.0;
+    for (int a = 0; a < m; ++a) {
+        lam_out[a] = std::max(lam[a], 1e-14 * lmax);
+        for (int i = 0; i < m; ++i) S_out[real[i] * P + a] = ms[i] * Q[(size_t)i * m + a];
+    }
+    int mode = m;
+    for (int a = 0; a < P; ++a)
+        if (idx[a] < 0) {
+            S_out[a * P + mode] = 1.0;
+            lam_out[mode++] = 1.0;
+        }
+}
+
 struct ColumnData {
-    std::vector<double> S;    // [n_cols][2][N*N]  S_xi, S_eta (row = node, column = mode)
-    std::vector<double> lam;  // [n_cols][2][N]    unit-modulus eigenvalues
+    int P = 0;                // patch width N + 2k (N without overlap)
+    std::vector<double> S;    // [n_cols][2][P*P]  S_xi, S_eta (row = node, column = mode)
+    std::vector<double> lam;  // [n_cols][2][P]    unit-modulus eigenvalues
+    std::vector<int> pg;      // [n_cols][P*P]     patch gather table (overlap only)
+    std::vector<int> ps;      // [n_cols][N*N][4]  patch sum table (overlap only)
     std::vector<double> rat;  // [n_cols][3][2]    horizontal modulus / c44 per component
     std::vector<double> V;    // [3][n][n]         z-eigenvectors (row = z node, column = mode)
     std::vector<double> Lz;   // [3][n]
 };
 
-void build_column(const dgtn_ctx* c, const Level& L, ColumnData& out) {
+void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& out) {
     const int N = L.N, N2 = N * N, nz = L.n_z, n = nz * N;
     const double yr = c->y_ref;
+    const int ko = std::max(0, std::min(overlap, N / 2));
+    out.P = N + 2 * ko;
     out.S.assign((size_t)L.n_cols * 2 * N2, 0.0);
     out.lam.assign((size_t)L.n_cols * 2 * N, 0.0);
+    std::vector<double> width((size_t)L.n_cols * 2, 0.0), sigf((size_t)L.n_cols * 4, 0.0);
     out.rat.assign((size_t)L.n_cols * 6, 1.0);
     // reference c11 / c44 for the horizontal moduli: the thickest layer's material
     int thick = 0;
@@ -460,13 +578,68 @@ void build_column(const dgtn_ctx* c, const Level& L, ColumnData& out) {
                 double s = 0;
                 for (int t = 0; t < N; ++t) s += L.sig_side[((size_t)col * 4 + f) * N + t];
                 sig[k] = s / N;
+                sigf[(size_t)col * 4 + f] = sig[k];
                 ends[k] = L.cnbr[col * 4 + f] >= 0 ? END_INTERIOR : end_type(L.cnf[col * 4 + f]);
             }
+            width[(size_t)col * 2 + d] = h;
             auto K = element_1d(L.lgl, h, ends[0], sig[0], ends[1], sig[1]);
             fdm_1d(L.lgl, h, K, &out.S[((size_t)col * 2 + d) * N2], &out.lam[((size_t)col * 2 + d) * N], 1.0);
             for (int cc = 0; cc < 2; ++cc)
                 out.rat[(size_t)col * 6 + cc * 2 + d] = r11 * dir[cc] * dir[cc] + (1.0 - dir[cc] * dir[cc]);
         }
+    }
+    if (ko > 0) {
+        // overlapping patches: 1D operators along (left neighbour, column, right
+        // neighbour) restricted to the k node lines next to each shared face
+        const int P = out.P, P2 = P * P;
+        out.S.assign((size_t)L.n_cols * 2 * P2, 0.0);
+        out.lam.assign((size_t)L.n_cols * 2 * P, 1.0);
+        for (int col = 0; col < L.n_cols; ++col)
+            for (int d = 0; d < 2; ++d) {
+                const int flo = 2 * d, fhi = 2 * d + 1;
+                const int nlo = L.cnbr[col * 4 + flo], nhi = L.cnbr[col * 4 + fhi];
+                std::vector<double> hs, sig_if;
+                if (nlo >= 0) {
+                    hs.push_back(width[(size_t)nlo * 2 + ((L.cnf[col * 4 + flo] & 3) >> 1)]);
+                    sig_if.push_back(sigf[(size_t)col * 4 + flo]);
+                }
+                const int own = (int)hs.size() * N;
+                hs.push_back(width[(size_t)col * 2 + d]);
+                if (nhi >= 0) {
+                    hs.push_back(width[(size_t)nhi * 2 + ((L.cnf[col * 4 + fhi] & 3) >> 1)]);
+                    sig_if.push_back(sigf[(size_t)col * 4 + fhi]);
+                }
+                const int lo = nlo >= 0 ? END_NONE : end_type(L.cnf[col * 4 + flo]);
+                const int hi = nhi >= 0 ? END_NONE : end_type(L.cnf[col * 4 + fhi]);
+                const auto K = line_1d(L.lgl, hs, sig_if, lo, sigf[(size_t)col * 4 + flo], hi,
+                                       sigf[(size_t)col * 4 + fhi]);
+                const int nline = (int)hs.size() * N;
+                std::vector<double> mass(nline);
+                for (int e = 0; e < (int)hs.size(); ++e)
+                    for (int i = 0; i < N; ++i) mass[e * N + i] = L.lgl.w[i] * 0.5 * hs[e];
+                std::vector<int> idx(P, -1);
+                for (int a = 0; a < P; ++a) {
+                    const int x = a - ko;
+                    if (x >= 0 && x < N) idx[a] = own + x;
+                    else if (x < 0 && nlo >= 0) idx[a] = own + x;
+                    else if (x >= N && nhi >= 0) idx[a] = own + x;
+                }
+                patch_fdm(K, nline, mass, idx, &out.S[((size_t)col * 2 + d) * P2], &out.lam[((size_t)col * 2 + d) * P]);
+            }
+        out.pg.assign((size_t)L.n_cols * P2, -1);
+        out.ps.assign((size_t)L.n_cols * N2 * 4, -1);
+        for (int col = 0; col < L.n_cols; ++col)
+            for (int b = 0; b < P; ++b)
+                for (int a = 0; a < P; ++a) {
+                    const int src = locate_node(L, col, a - ko, b - ko);
+                    out.pg[(size_t)col * P2 + b * P + a] = src;
+                    if (src < 0) continue;
+                    int* slot = &out.ps[(size_t)src * 4];
+                    int q = 0;
+                    while (q < 4 && slot[q] >= 0) ++q;
+                    if (q == 4) throw std::runtime_error("a node lies in more than four column patches");
+                    slot[q] = col * P2 + b * P + a;
+                }
     }
     // z: one generalized eigenproblem per component, K_z V = M V diag(lz), M = diag(c44 w h / 2)
     out.V.assign((size_t)3 * n * n, 0.0);
@@ -541,11 +714,28 @@ void build_transfer(const dgtn_ctx* c, const Level& F, const Level& C, Transfer&
 
 }  // namespace
 
+int solver_key(const dgtn_solve_opts* opts) {
+    if (!opts) return 2;
+    return 2 * std::max(1, opts->mg_levels) + 1 + 1000 * std::max(0, opts->overlap);
+}
+
 dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts) {
     const int want = opts ? std::max(1, opts->mg_levels) : 1;
     if (!c->solver) c->solver = new SolverState();
     SolverState& S = *c->solver;
-    const int key = 2 * want + (opts ? 1 : 0);
+    if (opts && (opts->overlap < 0 || opts->overlap > 3)) {
+        set_error("overlap must be 0..3");
+        return DGTN_EINVAL;
+    }
+    if (opts && opts->overlap > 0) {
+        // the patch kernels stage 2 x 3 N P^2 + 2 P^2 doubles in LDS
+        const int N = c->levels[0].N, P = N + 2 * std::min(opts->overlap, N / 2);
+        if (8 * (6 * N * P * P + 2 * P * P) > 65536) {
+            set_error("overlap too wide for this polynomial degree");
+            return DGTN_EINVAL;
+        }
+    }
+    const int key = solver_key(opts);
     if (S.key_levels == key && (int)S.mg.size() == (int)c->levels.size()) return DGTN_OK;
     c->levels.resize(1);
     int p = c->levels[0].N - 1, r = c->levels[0].refine;
@@ -561,8 +751,11 @@ dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts) {
         for (size_t l = 0; l < c->levels.size(); ++l) {
             build_fdm(c, c->levels[l], S.mg[l].fdm);
             ColumnData cd;
-            build_column(c, c->levels[l], cd);
+            build_column(c, c->levels[l], opts->overlap, cd);
             MgLevel& M = S.mg[l];
+            M.P = cd.P;
+            M.pg = std::move(cd.pg);
+            M.ps = std::move(cd.ps);
             M.cS = std::move(cd.S);
             M.clam = std::move(cd.lam);
             M.crat = std::move(cd.rat);
@@ -594,9 +787,14 @@ void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
             M.off_crat[pi] = lay.take(rs * M.crat.size());
             M.off_cV[pi] = lay.take(rs * M.cV.size());
             M.off_clz[pi] = lay.take(rs * M.clz.size());
-            M.off_cT[pi] = lay.take(rs * n);
-            M.off_cY[pi] = lay.take(rs * n);
+            const size_t np = M.P > 0 ? n / ((size_t)L.N * L.N) * M.P * M.P : n;
+            M.off_cT[pi] = lay.take(rs * np);
+            M.off_cY[pi] = lay.take(rs * np);
             M.off_b[pi] = lay.take(rs * n);
+            if (pi == 0) {
+                M.off_pg = lay.take(4 * M.pg.size());
+                M.off_ps = lay.take(4 * M.ps.size());
+            }
             M.off_x[pi] = lay.take(rs * n);
             M.off_t[pi] = lay.take(rs * n);
         }
@@ -679,6 +877,10 @@ dgtn_status bind_solver(dgtn_ctx* c, hipStream_t s) {
         if ((st = up2(M.off_crat, M.crat)) != DGTN_OK) return st;
         if ((st = up2(M.off_cV, M.cV)) != DGTN_OK) return st;
         if ((st = up2(M.off_clz, M.clz)) != DGTN_OK) return st;
+        if (!M.pg.empty()) {
+            if ((st = upload(c, M.off_pg, M.pg.data(), 4 * M.pg.size(), s)) != DGTN_OK) return st;
+            if ((st = upload(c, M.off_ps, M.ps.data(), 4 * M.ps.size(), s)) != DGTN_OK) return st;
+        }
     }
     for (auto& T : S.tr) {
         dgtn_status st = up2(T.off_I, T.I);
@@ -726,7 +928,12 @@ dgtn_status smooth(dgtn_ctx* c, int l, const VOpts& o, const R* b, const R* Ax, 
     const int pi = sizeof(R) == 8 ? 0 : 1;
     const Level& L = c->levels[l];
     MgLevel& M = S.mg[l];
-    if (o.smoother == DGTN_SMOOTH_COLUMN) {
+    if (o.smoother == DGTN_SMOOTH_COLUMN && M.P > L.N) {
+        SHIP(mg_ovl_smooth<R>(L.N, L.n_cols, L.n_z, M.P, at<int>(c, M.off_pg), at<int>(c, M.off_ps),
+                              at<R>(c, M.off_cS[pi]), at<R>(c, M.off_clam[pi]), at<R>(c, M.off_crat[pi]),
+                              at<R>(c, M.off_cV[pi]), at<R>(c, M.off_clz[pi]), b, Ax, x, (R)o.omega,
+                              at<R>(c, M.off_cT[pi]), at<R>(c, M.off_cY[pi]), s));
+    } else if (o.smoother == DGTN_SMOOTH_COLUMN) {
         SHIP(mg_col_smooth<R>(L.N, L.n_cols, L.n_z, at<R>(c, M.off_cS[pi]), at<R>(c, M.off_clam[pi]),
                               at<R>(c, M.off_crat[pi]), at<R>(c, M.off_cV[pi]), at<R>(c, M.off_clz[pi]), b, Ax, x,
                               (R)o.omega, at<R>(c, M.off_cT[pi]), at<R>(c, M.off_cY[pi]), s));
@@ -897,11 +1104,35 @@ extern "C" dgtn_status dgtn_smoother_block(dgtn_ctx* c, const dgtn_solve_opts* o
     return DGTN_OK;
 }
 
+extern "C" dgtn_status dgtn_patch_table(dgtn_ctx* c, const dgtn_solve_opts* opts, int level, int* P, int* table) {
+    if (!c || !opts || !P) { set_error("null argument"); return DGTN_EINVAL; }
+    try {
+        dgtn_status st = prepare_levels(c, opts);
+        if (st != DGTN_OK) return st;
+    } catch (const std::exception& ex) {
+        set_error(ex.what());
+        return DGTN_EINVAL;
+    }
+    if (level < 0 || level >= (int)c->levels.size()) { set_error("no such level"); return DGTN_EINVAL; }
+    const MgLevel& M = c->solver->mg[level];
+    const Level& L = c->levels[level];
+    *P = M.P;
+    if (table) {
+        if (M.pg.empty()) {  // no overlap: every column's patch is its own grid
+            for (int col = 0; col < L.n_cols; ++col)
+                for (int q = 0; q < L.N * L.N; ++q) table[(size_t)col * L.N * L.N + q] = col * L.N * L.N + q;
+        } else {
+            std::copy(M.pg.begin(), M.pg.end(), table);
+        }
+    }
+    return DGTN_OK;
+}
+
 extern "C" dgtn_status dgtn_precondition(dgtn_ctx* c, const dgtn_solve_opts* opts, const double* v, double* z,
                                          hipStream_t s) {
     if (!c || !opts || !v || !z) { set_error("null argument"); return DGTN_EINVAL; }
     if (!c->bound || !c->has_opts || !c->solver || !c->solver->planned ||
-        2 * std::max(1, opts->mg_levels) + 1 != c->solver->key_levels) {
+        solver_key(opts) != c->solver->key_levels) {
         set_error("bind a workspace with these solve options first");
         return DGTN_EINVAL;
     }
@@ -922,8 +1153,10 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     if (opts->precond_precision != 64 && opts->precond_precision != 32) {
         set_error("precond_precision must be 64 or 32"); return DGTN_EINVAL;
     }
-    if (opts->mg_levels < 0 || 2 * std::max(1, opts->mg_levels) + 1 != c->solver->key_levels || std::max(4, opts->restart) > c->solver->m || opts->restart < 1) {
-        set_error("solve options differ from the bound ones (mg_levels/restart)"); return DGTN_EINVAL;
+    if (opts->mg_levels < 0 || solver_key(opts) != c->solver->key_levels ||
+        std::max(4, opts->restart) > c->solver->m || opts->restart < 1) {
+        set_error("solve options differ from the bound ones (mg_levels/overlap/restart)");
+        return DGTN_EINVAL;
     }
     if (!(opts->rtol > 0) || opts->max_iter < 1 || opts->smooth_steps < 1 || !(opts->smooth_damping > 0)) {
         set_error("invalid solve options"); return DGTN_EINVAL;

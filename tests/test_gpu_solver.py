@@ -148,3 +148,49 @@ def test_noise_from_solved_energies():
     from oracle import physics
     S = P.noise(U, [1e-6] * len(U), 295.0, 100.0)
     assert abs(S / physics.noise_psd(g["U_layers"], [1e-6] * len(U), 295.0, 100.0, 1.0) - 1) < 1e-10
+
+
+def test_overlap_on_a_single_column_equals_no_overlap():
+    # one column: the patch has no neighbours, so the overlapping solve is the plain one
+    spec = W.box(nx=1, ny=1, Lx=0.7, Ly=0.4, p=4,
+                 layers=[{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
+                         {"thickness": 0.6, "n_elem": 3, "ratio": 1.5, "material": 0}],
+                 materials=[W.FUSED_SILICA, W.CRYSTAL_A])
+    P = dgtn.Problem(spec)
+    v = _dev(W.random_field(spec, 7))
+    out = []
+    for ov in (0, 2):
+        o = dgtn.default_opts(64, mg_levels=1, overlap=ov)
+        P.bind(o)
+        out.append(P.precondition(v, o).cpu().numpy())
+    assert np.max(np.abs(out[0] - out[1])) < 1e-12 * np.max(np.abs(out[0]))
+
+
+@pytest.mark.parametrize("overlap", [1, 2])
+def test_overlapping_preconditioner_is_symmetric_positive(overlap):
+    spec = W.config1()
+    P = dgtn.Problem(spec)
+    o = dgtn.default_opts(64, mg_levels=1, overlap=overlap)
+    P.bind(o)
+    v = _dev(W.random_field(spec, 1))
+    w = _dev(W.random_field(spec, 2))
+    Mv, Mw = P.precondition(v, o), P.precondition(w, o)
+    a, b = float(torch.sum(w * Mv)), float(torch.sum(v * Mw))
+    assert abs(a - b) < 1e-12 * float(torch.linalg.norm(v) * torch.linalg.norm(Mw))
+    assert float(torch.sum(v * Mv)) > 0 and float(torch.sum(w * Mw)) > 0
+
+
+@pytest.mark.parametrize("name", ["config1", "config3_seed0"])
+def test_overlapping_schwarz_cuts_iterations_and_keeps_the_energy(name):
+    g = _golden(name)
+    spec = g["spec"]
+    P = dgtn.Problem(spec)
+    its = {}
+    for ov in (0, 1):
+        o = dgtn.default_opts(64, rtol=1e-11, max_iter=20000, overlap=ov)
+        P.bind(o)
+        u, st = P.solve(opts=o)
+        its[ov] = st.iters
+        U = P.energy(u)
+        np.testing.assert_allclose(U, g["U_layers"], rtol=1e-9)
+    assert its[1] * 5 < its[0], its
