@@ -4,13 +4,17 @@ Workload: the thin-coating cylinder (2000 hexahedra at p = 6, 2,058,000 DoF;
 coating 1e-3 R of 140 GPa / 0.23 on fused silica, 24 graded substrate
 elements), synthetic seeded inputs resident in HBM.
 
-A timed step is one pass of the hot path over the workload: the load vector,
-the preconditioned Krylov solve (FP32 preconditioner inside FP64 FGMRES),
-the layer energies and S_x.  The headline value is the DG-apply throughput
-(FP64 operator applications per second times DoF), measured with HIP events
-on the stream the kernels run on; the JSON line also carries the FP32 apply
-rate, time-to-U of the FP64- and FP32-preconditioned solves, the roofline of
-the dominant kernel and the oracle's CPU rate on a bounded sample.
+One timed step is one pass of the whole hot path over the workload: the load
+vector; a block of FP64 operator applications (the DG apply, timed with HIP
+events on the stream it runs on); the FP32-preconditioned flexible-CG solve at
+the stopping tolerance calibrated for a 1e-8 error in the layer energies; the
+energies and S_x; and the adjoint gradient of S_x with respect to (Y_coat,
+nu_coat, Y_sub, nu_sub, coating thickness), i.e. one more solve and the
+parameter derivatives.  The headline value is the DG-apply throughput (DoF x
+applications / s) of the apply blocks inside the timed steps; the JSON line
+also carries the step breakdown, the FP32 apply rate, time-to-U of the FP64-
+and FP32-preconditioned solves, the roofline of the dominant kernel and the
+oracle's CPU rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -142,7 +146,9 @@ def time_to_u(P, target=1e-8, log=None):
         dt = time.perf_counter() - t0
         return U, st, dt
 
-    Uref, st, dt = solve(64, 1e-11)
+    # FP64 residuals stagnate near 3e-10 on this workload: the reference runs to
+    # that floor (ENOCONV is expected there) and its energies are stable to ~1e-12
+    Uref, st, dt = solve(64, 1e-11, max_iter=3000)
     if log:
         log(f"reference solve: {st.iters} iterations, rel.res {st.rel_res:.2e}, {dt:.2f} s")
     out = {"reference": {"U": float(Uref.sum()), "U_layers": Uref.tolist(), "iters": st.iters,
@@ -160,7 +166,8 @@ def time_to_u(P, target=1e-8, log=None):
         if chosen is None:
             out[f"fp{prec}_precond"] = None
             continue
-        U, st, dt = solve(prec, chosen)  # timed at the calibrated tolerance
+        runs = [solve(prec, chosen) for _ in range(3)]  # timed at the calibrated tolerance
+        U, st, dt = sorted(runs, key=lambda r: r[2])[1]
         err = float(np.max(np.abs(U - Uref) / np.abs(Uref)))
         out[f"fp{prec}_precond"] = {"time_to_U_s": dt, "iters": st.iters, "rtol": chosen,
                                     "U_rel_err": err, "ms_per_iter": dt / max(st.iters, 1) * 1e3}
@@ -204,12 +211,13 @@ def main():
     spec = W.config2()
     n_dof = W.n_dof(spec)
     P = dgtn.Problem(spec)
-    P.bind()
+    P.bind(dgtn.default_opts(32))
     stream = torch.cuda.current_stream()
     u64 = torch.from_numpy(W.random_field(spec, seed=0)).cuda()
     u32 = u64.float()
     o64 = torch.empty_like(u64)
     o32 = torch.empty_like(u32)
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)  # noqa: E731
 
     def app64():
         P.apply(u64, o64)
@@ -217,18 +225,52 @@ def main():
     def app32():
         P.apply(u32, o32)
 
-    for _ in range(args.warmup * args.reps):
-        app64()
+    # calibration of the stopping tolerances (untimed): time-to-U of both preconditioners
+    ttu = None
+    rtol32 = 1e-8
+    if not args.no_solve:
+        ttu = time_to_u(P, log=log)
+        if ttu.get("fp32_precond"):
+            rtol32 = ttu["fp32_precond"]["rtol"]
+    opts32 = dgtn.default_opts(32, rtol=rtol32, max_iter=20000)
+    grad_params = [("youngs", 1), ("poisson", 1), ("youngs", 0), ("poisson", 0), ("thickness", 0)]
+    T_K, f_Hz, phi = 300.0, 100.0, np.array([4e-4, 1e-7])   # synthetic loss angles (coating, substrate)
+    w_sx = 4 * 1.380649e-23 * T_K * phi / (np.pi * f_Hz * spec["load"]["F0"] ** 2)
+
+    def step():
+        """One pass of the hot path; returns (apply block seconds, breakdown)."""
+        b = P.rhs()
+        t_app = time_launches(app64, args.reps, stream)
+        rec = {}
+        if not args.no_solve:
+            t0 = time.perf_counter()
+            u, st = P.solve(b, opts=opts32, raise_on_noconv=False)
+            U = P.energy(u)
+            rec["S_x"] = P.noise(U, phi, T_K, f_Hz)
+            t1 = time.perf_counter()
+            lam, st2 = P.solve(P.energy_grad(u, w_sx), opts=opts32, raise_on_noconv=False)
+            rec["dSx_dtheta"] = P.grad(u, lam, grad_params, w_sx).tolist()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec.update(U_layers=U.tolist(), solve_iters=st.iters, adjoint_iters=st2.iters,
+                       solve_s=t1 - t0, adjoint_s=t2 - t1)
+        return t_app, rec
+
+    for _ in range(args.warmup):
+        step()
         app32()
     torch.cuda.synchronize()
-
-    # timed steps: the full operator application, FP64 (headline) and FP32
-    t64, t32 = [], []
+    t_steps, t_apps, recs = [], [], []
     for _ in range(args.steps):
-        t64.append(time_launches(app64, args.reps, stream))
-        t32.append(time_launches(app32, args.reps, stream))
-    torch.cuda.synchronize()
-    a64 = float(np.median(t64))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_app, rec = step()
+        torch.cuda.synchronize()
+        t_steps.append(time.perf_counter() - t0)
+        t_apps.append(t_app)
+        recs.append(rec)
+    a64 = float(np.median(t_apps))
+    t32 = [time_launches(app32, args.reps, stream) for _ in range(max(3, args.steps // 4))]
     a32 = float(np.median(t32))
 
     # per-kernel durations for the roofline (same stream, HIP events)
@@ -248,7 +290,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": a64 * args.reps * 1e3,
+        "ms_per_step": float(np.mean(t_steps)) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -257,7 +299,15 @@ def main():
         "config": {"workload": "thin-coating cylinder, 2000 hex elements, p=6, 2,058,000 DoF "
                                "(coating 1e-3 R, 140 GPa/0.23 on 72 GPa/0.17, 24 graded substrate elements)",
                    "n_dof": n_dof, "elements": W.n_elements(spec), "p": spec["p"],
-                   "applies_per_step": args.reps},
+                   "applies_per_step": args.reps, "precond": "fp32, overlapping column Schwarz (overlap 1)",
+                   "solve_rtol": rtol32},
+        "step": {"apply_block_ms": a64 * args.reps * 1e3,
+                 "solve_ms": float(np.median([r.get("solve_s", 0) for r in recs])) * 1e3,
+                 "adjoint_ms": float(np.median([r.get("adjoint_s", 0) for r in recs])) * 1e3,
+                 "solve_iters": recs[-1].get("solve_iters"), "adjoint_iters": recs[-1].get("adjoint_iters"),
+                 "U_layers": recs[-1].get("U_layers"), "S_x": recs[-1].get("S_x"),
+                 "dSx_dtheta": recs[-1].get("dSx_dtheta"),
+                 "theta": ["Y_coat", "nu_coat", "Y_sub", "nu_sub", "d_coat"]},
         "apply_fp64_us": a64 * 1e6,
         "apply_fp32_us": a32 * 1e6,
         "apply_fp32_dof_per_s": n_dof / a32,
@@ -275,8 +325,8 @@ def main():
     traffic = measured_traffic()
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
-    if not args.no_solve:
-        out["time_to_U"] = time_to_u(P, log=lambda s: print("[bench] " + s, file=sys.stderr, flush=True))
+    if ttu is not None:
+        out["time_to_U"] = ttu
         t64 = (out["time_to_U"].get("fp64_precond") or {}).get("time_to_U_s")
         t32 = (out["time_to_U"].get("fp32_precond") or {}).get("time_to_U_s")
         if t64 and t32:

@@ -236,7 +236,7 @@ dgtn_status dgtn_energy_grad(dgtn_ctx* ctx, const double* u, const double* w_lay
  * symmetric; the load does not depend on the parameters).  A_theta u and
  * K_w,theta are evaluated exactly by the operator and energy kernels on dual
  * numbers.  u, lam: device double; dJ: host, n_params values.  Available for
- * p <= 5 (DGTN_EINVAL otherwise).  Synchronises the stream. */
+ * p <= 6 (DGTN_EINVAL otherwise).  Synchronises the stream. */
 dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const double* w_layers,
                       int n_params, const dgtn_param* params, double* dJ, hipStream_t stream);
 

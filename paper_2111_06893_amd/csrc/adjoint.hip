@@ -77,6 +77,11 @@ LevelView<Dual> dual_view(const dgtn_ctx* c) {
     v.bc_top = c->prob.bc_top;
     v.bc_bottom = c->prob.bc_bottom;
     v.penalty_n2 = Dual(L.pen_z, 0.0);
+    for (int q = 0; q < 64; ++q) {
+        const bool in = q < L.N * L.N;
+        v.Dk[q] = Dual(in ? L.lgl.D[q] : 0.0, 0.0);
+        v.Dt[q] = Dual(in ? L.lgl.D[(q % L.N) * L.N + q / L.N] : 0.0, 0.0);
+    }
     return v;
 }
 
@@ -96,7 +101,7 @@ void plan_adjoint(dgtn_ctx* c, Layout& lay) {
     AdjointLayout& A = c->adj;
     const size_t N = L.N, N2 = N * N, n = ndof(L), ds = sizeof(Dual);
     A.wz = lay.take(8 * (size_t)L.n_z);
-    A.ok = L.N <= 6;
+    A.ok = L.N <= 7;
     if (!A.ok) return;
     A.u = lay.take(ds * n);
     A.Au = lay.take(ds * n);
@@ -171,7 +176,7 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
     }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     const AdjointLayout& A = c->adj;
-    if (!A.ok) { set_error("parameter derivatives are available for p <= 5"); return DGTN_EINVAL; }
+    if (!A.ok) { set_error("parameter derivatives are available for p <= 6"); return DGTN_EINVAL; }
     const Level& L = c->levels[0];
     const int nmat = (int)c->prob.materials.size(), nlay = (int)c->prob.layers.size();
     for (int i = 0; i < n_params; ++i) {

@@ -44,6 +44,11 @@ LevelView<R> view_of(const dgtn_ctx* c, const Level& L) {
     v.bc_top = c->prob.bc_top;
     v.bc_bottom = c->prob.bc_bottom;
     v.penalty_n2 = R(L.pen_z);
+    for (int q = 0; q < 64; ++q) {
+        const bool in = q < L.N * L.N;
+        v.Dk[q] = in ? R(L.lgl.D[q]) : R(0);
+        v.Dt[q] = in ? R(L.lgl.D[(q % L.N) * L.N + q / L.N]) : R(0);
+    }
     return v;
 }
 template LevelView<double> view_of<double>(const dgtn_ctx*, const Level&);

@@ -38,6 +38,10 @@ struct LevelView {
     const R* w;          // [N]
     int bc_top, bc_bottom;
     R penalty_n2;        // C * N^2
+    // D by value: the kernels read it from the kernel-argument segment with
+    // wave-uniform indices, i.e. through scalar loads instead of LDS.
+    R Dk[64];            // D[x * N + a], N <= 8
+    R Dt[64];            // D^T
 };
 
 // Host description of one level (mesh + geometry), built from the problem.

@@ -1,10 +1,13 @@
 // gfx950 kernels of the DG elasticity operator (Sec. 2.2.2 - 2.2.4).
 //
-// One workgroup per element, one lane per LGL node (N^3 lanes rounded up to
-// whole 64-wide waves).  The element's displacement is staged in LDS, the
-// reference derivatives are LGL contractions along the three tensor
-// directions, and everything pointwise (metric, lift, constitutive relation,
-// fluxes) stays in registers.  FP64 and FP32 are the same template.
+// One workgroup per element.  The element's displacement is staged in LDS and
+// the work alternates between three lane roles separated by barriers: line
+// lanes (one per line of N nodes along xi, eta or zeta and per component) do
+// the sum-factorised LGL contractions, reading each input once from LDS with
+// the 1D matrix D in scalar registers; node lanes (one per LGL node) do the
+// pointwise metric, lift and constitutive work; face lanes (one per face node)
+// do the jumps and numerical fluxes.  FP64, FP32 and the dual numbers of the
+// adjoint are the same template.
 //
 // The operator is applied in two passes:
 //   k_traction  t = n . Y . D u on the 6 N^2 face nodes of every element (the
@@ -225,13 +228,6 @@ __device__ __forceinline__ void load_faces(const LevelView<R>& L, int col, int i
     }
 }
 
-// Lanes per workgroup: one per node for the volume work, one per face node
-// (6 N^2) for the face work, rounded up to whole 64-wide waves.
-template <int N>
-constexpr int apply_threads() {
-    return ((((N * N * N) > (6 * N * N) ? (N * N * N) : (6 * N * N)) + 63) / 64) * 64;
-}
-
 // Node (i, j, k) of face node fi on face f (the face-buffer order).
 template <int N>
 __device__ __forceinline__ void face_node(int f, int fi, int& i, int& j, int& k) {
@@ -242,19 +238,90 @@ __device__ __forceinline__ void face_node(int f, int fi, int& i, int& j, int& k)
     else { i = a; j = b; k = s; }
 }
 
+// Lanes of the operator kernels: 9 N^2 line tasks (3 directions x 3 components
+// x N^2 lines), N^3 nodes, 6 N^2 face nodes, rounded up to whole waves.
+template <int N>
+constexpr int line_threads() {
+    constexpr int a = 9 * N * N, b = N * N * N, c = 6 * N * N;
+    constexpr int m = a > b ? (a > c ? a : c) : (b > c ? b : c);
+    return ((m + 63) / 64) * 64;
+}
+
+// Line task t < 9 N^2: direction d (xi, eta, zeta), component c, and the offset
+// and stride of the line's N nodes within one component's N^3 block.
+template <int N>
+__device__ __forceinline__ void line_of(int t, int& d, int& c, int& base, int& stride) {
+    constexpr int N2 = N * N;
+    d = t / (3 * N2);
+    const int rem = t % (3 * N2);
+    c = rem / N2;
+    const int q = rem % N2, q1 = q % N, q2 = q / N;
+    base = d == 0 ? q2 * N2 + q1 * N : d == 1 ? q2 * N2 + q1 : q2 * N + q1;
+    stride = d == 0 ? 1 : d == 1 ? N : N2;
+}
+
+// Sum-factorised 1D contraction along one line, one lane per line: the N
+// inputs are read from LDS once, D comes from the kernel arguments (uniform
+// across the wave, so it sits in scalar registers).
+//   transpose = false: dst[x] = sum_a D[x][a] src[a]   (derivative)
+//   transpose = true:  dst[x] = sum_a D[a][x] src[a]   (weak divergence)
+// emit(x, value) consumes output x.
+template <int N, bool transpose, typename R, typename Emit>
+__device__ __forceinline__ void line_contract(const LevelView<R>& L, const R* src, int base, int stride, Emit&& emit) {
+    R v[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[a] = src[base + a * stride];
+    // one row of D (or D^T) per output, loaded as the loop reaches it: the
+    // whole matrix would not fit the scalar register file
+#pragma unroll 1
+    for (int x = 0; x < N; ++x) {
+        const R* row = (transpose ? L.Dt : L.Dk) + x * N;
+        R acc = 0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc += row[a] * v[a];
+        emit(x, acc);
+    }
+}
+
+// Reference derivatives of the three components along the three directions,
+// sG[(d * 3 + c) * N^3 + node], from the LDS copy of u.
 template <int N, typename R>
-__global__ __launch_bounds__(apply_threads<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
-                                                                R* __restrict__ tau) {
+__device__ __forceinline__ void ref_derivatives(const LevelView<R>& L, const R* su, R* sG, int tid) {
+    constexpr int N3 = N * N * N;
+    if (tid < 9 * N * N) {
+        int d, c, base, stride;
+        line_of<N>(tid, d, c, base, stride);
+        R* dst = sG + (d * 3 + c) * N3 + base;
+        line_contract<N, false>(L, su + c * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
+    }
+}
+
+// Physical gradient G[d][l] = D_d u_l at node q from the reference derivatives.
+template <int N, typename R>
+__device__ __forceinline__ void node_gradient(const R* sG, int q, const NodeGeo<R>& g, R G[3][3]) {
+    constexpr int N3 = N * N * N;
+    const R dz = R(2) / g.hz;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const R dxi = sG[l * N3 + q], deta = sG[(3 + l) * N3 + q], dzeta = sG[(6 + l) * N3 + q];
+        G[0][l] = g.axx * dxi + g.aex * deta;
+        G[1][l] = g.axy * dxi + g.aey * deta;
+        G[2][l] = dz * dzeta;
+    }
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
+                                                               R* __restrict__ tau) {
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ R su[3 * N3];
-    __shared__ R sD[N2];
+    __shared__ R sG[9 * N3];
     __shared__ R sown[4];
     const int e = xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
     for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
     if (tid == 0) {
         const int m = L.zmat[iz];
         sown[0] = L.mat[3 * m];
@@ -268,10 +335,12 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_traction(LevelView<R> L,
     if (act) face_node<N>(f, fi, i, j, k);
     NodeGeo<R> g = act ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
     __syncthreads();
+    ref_derivatives<N>(L, su, sG, tid);
+    __syncthreads();
     if (!act) return;
     g.hz = sown[3];
     R G[3][3], S[6], T[6], n[3], amag, t[3];
-    gradient<N>(su, sD, i, j, k, g, G);
+    node_gradient<N>(sG, k * N2 + j * N + i, g, G);
     sym_of(G, S);
     cubic_stress(sown[0], sown[1], sown[2], S, T);
     face_normal(f, g, n, amag);
@@ -283,24 +352,23 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_traction(LevelView<R> L,
 }
 
 template <int N, typename R>
-__global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, const R* __restrict__ u,
-                                                             const R* __restrict__ tau, R* __restrict__ out,
-                                                             R scale) {
+__global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, const R* __restrict__ u,
+                                                            const R* __restrict__ tau, R* __restrict__ out,
+                                                            R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
-    __shared__ R sbuf[9 * N3];        // the element's u (3 N^3), later the fluxes F (9 N^3)
+    static_assert(3 * N3 <= 36 * N2, "the eta part of the divergence reuses the lift buffer");
+    __shared__ R su[3 * N3];          // u; later the xi part of the weak divergence
+    __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
-    __shared__ R sLF[6 * 6 * N2];     // per face node: lift of the auxiliary-variable flux into S
-    __shared__ R sD[N2];
+    __shared__ R sLF[6 * 6 * N2];     // per face node: lift into S; later the eta part of the divergence
     __shared__ R sw[N];
     __shared__ FaceInfo<R> sface[6];
     __shared__ R sown[4];
-    R* su = sbuf;
     const int e = xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
     for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
     for (int q = tid; q < N; q += blockDim.x) sw[q] = L.w[q];
     load_faces<N>(L, col, iz, tid, sface, sown);
     // node role
@@ -317,7 +385,7 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, co
     __syncthreads();
     g.hz = sown[3];
     gf.hz = sown[3];
-    // neighbour trace and traction of this face node: in flight during the gradient
+    // neighbour trace and traction of this face node: in flight during the derivatives
     const FaceInfo<R> fo = sface[fact ? f : 0];
     R un[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     if (fact && fo.bc == 0) {
@@ -333,12 +401,15 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, co
         }
     }
     const R c11 = sown[0], c12 = sown[1], c44 = sown[2];
-    // 1. node lanes: unlifted gradient and stress; interior traction on each face slot
+    // 1. line lanes: reference derivatives of u
+    ref_derivatives<N>(L, su, sG, tid);
+    __syncthreads();
+    // 2. node lanes: unlifted gradient and stress; interior traction on each face slot
     R S[6];
     const bool fxi = (i == 0) | (i == N - 1), feta = (j == 0) | (j == N - 1), fzeta = (k == 0) | (k == N - 1);
     if (nact) {
         R G[3][3], T[6];
-        gradient<N>(su, sD, i, j, k, g, G);
+        node_gradient<N>(sG, tid, g, G);
         sym_of(G, S);
         if (fxi | feta | fzeta) {
             cubic_stress(c11, c12, c44, S, T);
@@ -358,7 +429,7 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, co
         }
     }
     __syncthreads();
-    // 2. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
+    // 3. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
     if (fact) {
         R n[3], amag;
         face_normal(f, gf, n, amag);
@@ -400,8 +471,7 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, co
         for (int c = 0; c < 3; ++c) sFT[slot + c * N2] = -wsig * flux[c];
     }
     __syncthreads();
-    // 3. node lanes: lifted strain, stress and the volume fluxes F
-    R Fr[9];
+    // 4. node lanes: lifted strain, stress and the volume fluxes F^m_c = w J (J^-1)^m_d T^{dc}
     if (nact) {
         const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
                               fzeta ? (k == 0 ? 4 : 5) : -1};
@@ -416,53 +486,40 @@ __global__ __launch_bounds__(apply_threads<N>()) void k_apply(LevelView<R> L, co
         cubic_stress(c11, c12, c44, S, T);
         const R wJ = sw[i] * sw[j] * sw[k] * g.det2 * R(0.5) * g.hz;
         const R dz = R(2) / g.hz;
-        // F^m_c = w J (J^-1)^m_d T^{dc}
         const R Tx[3] = {T[0], T[3], T[4]};
         const R Ty[3] = {T[3], T[1], T[5]};
         const R Tz[3] = {T[4], T[5], T[2]};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Fr[c] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
-            Fr[3 + c] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
-            Fr[6 + c] = wJ * dz * Tz[c];
+            sG[c * N3 + tid] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
+            sG[(3 + c) * N3 + tid] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
+            sG[(6 + c) * N3 + tid] = wJ * dz * Tz[c];
         }
-    }
-    __syncthreads();  // every lane is done reading u from LDS
-    R* sF = sbuf;
-    if (nact) {
-        const int qn = k * N2 + j * N + i;
-#pragma unroll
-        for (int s = 0; s < 9; ++s) sF[s * N3 + qn] = Fr[s];
     }
     __syncthreads();
-    if (!nact) return;
-    // 4. weak divergence plus the face fluxes
-    R facc[3] = {0, 0, 0};
-    {
-        const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
-                              fzeta ? (k == 0 ? 4 : 5) : -1};
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (faces[q] < 0) continue;
-            const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) facc[c] += sFT[slot + c * N2];
-        }
+    // 5. weak divergence sum_m D_m^T F^m: xi and eta lines into su and sLF ...
+    if (tid < 6 * N2) {
+        int d, c, base, stride;
+        line_of<N>(tid, d, c, base, stride);
+        R* dst = (d == 0 ? su : sLF) + c * N3 + base;
+        line_contract<N, true>(L, sG + (d * 3 + c) * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
     }
-    R* oe = out + (size_t)e * 3 * N3;
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        R r = 0;
-        const R* Fx = sF + (0 + c) * N3;
-        const R* Fy = sF + (3 + c) * N3;
-        const R* Fz = sF + (6 + c) * N3;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            r += sD[a * N + i] * Fx[k * N2 + j * N + a];
-            r += sD[a * N + j] * Fy[k * N2 + a * N + i];
-            r += sD[a * N + k] * Fz[a * N2 + j * N + i];
-        }
-        oe[c * N3 + tid] = scale * (r + facc[c]);
+    __syncthreads();
+    // ... then the zeta lines add both, and the face fluxes, and write A u
+    if (tid < 3 * N2) {
+        const int c = tid / N2, q = tid % N2, ii = q % N, jj = q / N;
+        R* oe = out + (size_t)e * 3 * N3 + c * N3 + q;
+        const R* fx = (ii == 0 || ii == N - 1) ? sFT + (ii == 0 ? 0 : 1) * 3 * N2 + c * N2 + jj : nullptr;
+        const R* fy = (jj == 0 || jj == N - 1) ? sFT + (jj == 0 ? 2 : 3) * 3 * N2 + c * N2 + ii : nullptr;
+        line_contract<N, true>(L, sG + (6 + c) * N3, q, N2, [&](int x, R v) {
+            const int node = x * N2 + q;
+            R r = v + su[c * N3 + node] + sLF[c * N3 + node];
+            if (fx) r += fx[x * N];                                   // face_index(xi face) = k * N + j
+            if (fy) r += fy[x * N];                                   // face_index(eta face) = k * N + i
+            if (x == 0) r += sFT[4 * 3 * N2 + c * N2 + q];            // zeta-: j * N + i
+            if (x == N - 1) r += sFT[5 * 3 * N2 + c * N2 + q];        // zeta+
+            oe[x * N2] = scale * r;
+        });
     }
 }
 
@@ -618,7 +675,7 @@ template <typename R>
 hipError_t launch_traction(const LevelView<R>& L, const R* u, R* tau, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -627,7 +684,7 @@ template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }
@@ -669,6 +726,7 @@ hipError_t dispatch_dual(int N, F&& f) {
         case 4: return f(std::integral_constant<int, 4>{});
         case 5: return f(std::integral_constant<int, 5>{});
         case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
         default: return hipErrorInvalidValue;
     }
 }
@@ -677,7 +735,7 @@ template <>
 hipError_t launch_traction<Dual>(const LevelView<Dual>& L, const Dual* u, Dual* tau, hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, Dual>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, Dual>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -687,7 +745,7 @@ hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dua
                               hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(apply_threads<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }

@@ -315,77 +315,100 @@ __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, con
     x[o] = (accumulate ? x[o] : R(0)) + omega * acc;
 }
 
-// Batched (over the 3 components, blockIdx.z) tiled product along z:
+// Batched (over the 3 components, blockIdx.z) product along z:
 //   trans = 1:  Y[i][m] = (sum_z V[z][i] T[z][m]) / (lz[i] + rx lx_a + ry ly_b)
 //   trans = 0:  T[z][m] =  sum_i V[z][i] Y[i][m]
-// V [3][n][n] row = z node, column = mode; in/out [3][n][ncol], m = col*N2 + b*N + a.
-constexpr int kTM = 64, kTN = 64, kTK = 16;
+// V [3][n][n] row = z node, column = mode; in/out [3][n][ncol], m = col*N2 + b*N + a,
+// computed on the matrix cores: 16 x 16 x 4 MFMA blocks (FP64 or FP32
+// inputs and accumulation).  A workgroup of four waves owns a 64 x 64 output
+// tile, each wave a 32 x 32 quarter as 2 x 2 blocks; K is staged through LDS in
+// chunks of 16.  Lane l of a block holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// its four results are C[row(l, q)][l % 16], q = 0..3, with row = 4 (l / 16) + q
+// for the FP32 instruction and row = 4 q + l / 16 for the FP64 one (measured).
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <typename R> struct MfmaAcc;
+template <> struct MfmaAcc<double> {
+    using type = d4_t;
+    __device__ static type step(double a, double b, type c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int q) { return 4 * q + lane / 16; }
+};
+template <> struct MfmaAcc<float> {
+    using type = f4_t;
+    __device__ static type step(float a, float b, type c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int q) { return 4 * (lane / 16) + q; }
+};
+
+constexpr int kGM = 64, kGN = 64, kGK = 16, kGPad = 4;
 template <typename R>
-__global__ __launch_bounds__(256) void k_col_gemm(int n, int ncol, int N, int trans, const R* __restrict__ V,
-                                                  const R* __restrict__ in, R* __restrict__ out,
-                                                  const R* __restrict__ lz, const R* __restrict__ lam,
-                                                  const R* __restrict__ rat) {
-    __shared__ R As[kTK][kTM];
-    __shared__ R Bs[kTK][kTN];
+__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, int trans, const R* __restrict__ V,
+                                                       const R* __restrict__ in, R* __restrict__ out,
+                                                       const R* __restrict__ lz, const R* __restrict__ lam,
+                                                       const R* __restrict__ rat) {
+    using Acc = MfmaAcc<R>;
+    __shared__ R As[kGK][kGM + kGPad];  // As[k][row]
+    __shared__ R Bs[kGK][kGN + kGPad];  // Bs[k][col]
     const int c = blockIdx.z;
-    const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int row0 = blockIdx.y * kGM, col0 = blockIdx.x * kGN;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
     const R* Vc = V + (size_t)c * n * n;
     const R* Bc = in + (size_t)c * n * ncol;
-    R acc[4][4];
+    typename Acc::type acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0;
-    for (int k0 = 0; k0 < n; k0 += kTK) {
-        for (int q = tid; q < kTK * kTM; q += 256) {
-            const int kk = q / kTM, rr = q % kTM;
+        for (int b = 0; b < 2; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+        for (int q = tid; q < kGK * kGM; q += 256) {
+            int kk, rr;
+            if (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
+            else { rr = q / kGK; kk = q % kGK; }         // V[row][k]: k contiguous
             const int kg = k0 + kk, rg = row0 + rr;
             R v = 0;
             if (kg < n && rg < n) v = trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg];
             As[kk][rr] = v;
         }
-        for (int q = tid; q < kTK * kTN; q += 256) {
-            const int kk = q / kTN, cc = q % kTN;
+        for (int q = tid; q < kGK * kGN; q += 256) {
+            const int kk = q / kGN, cc = q % kGN;
             const int kg = k0 + kk, cg = col0 + cc;
             Bs[kk][cc] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kTK; ++kk) {
-            R a[4], b[4];
+        for (int ks = 0; ks < kGK; ks += 4) {
+            R af[2], bf[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk][ty * 4 + q];
-                b[q] = Bs[kk][tx * 4 + q];
-            }
+            for (int a = 0; a < 2; ++a) af[a] = As[ks + lane / 16][wr + 16 * a + lane % 16];
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + lane / 16][wc + 16 * b + lane % 16];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = Acc::step(af[a], bf[b], acc[a][b]);
         }
         __syncthreads();
     }
     const int N2 = N * N;
     R* Oc = out + (size_t)c * n * ncol;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int rg = row0 + ty * 4 + p;
-        if (rg >= n) continue;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int cg = col0 + tx * 4 + q;
+        for (int b = 0; b < 2; ++b) {
+            const int cg = col0 + wc + 16 * b + lane % 16;
             if (cg >= ncol) continue;
-            R v = acc[p][q];
-            if (trans) {
-                const int colm = cg / N2, ab = cg % N2, bb = ab / N, aa = ab % N;
-                const R den = lz[(size_t)c * n + rg] + rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * N + aa] +
-                              rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * N + bb];
-                v /= den;
+            const int colm = cg / N2, ab = cg % N2, bb = ab / N, aa = ab % N;
+            const R lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * N + aa] +
+                          rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * N + bb];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rg = row0 + wr + 16 * a + Acc::row(lane, q);
+                if (rg >= n) continue;
+                R v = acc[a][b][q];
+                if (trans) v /= lz[(size_t)c * n + rg] + lxy;
+                Oc[(size_t)rg * ncol + cg] = v;
             }
-            Oc[(size_t)rg * ncol + cg] = v;
         }
-    }
 }
 
 // Fine += P coarse over the same elements, P = I (x) I (x) I with I [Nf][Nc].
@@ -735,9 +758,9 @@ hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, c
         return hipGetLastError();
     });
     if (err != hipSuccess) return err;
-    const dim3 grid((ncol + kTN - 1) / kTN, (n + kTM - 1) / kTM, 3);
-    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, N, 1, V, T, Y, lz, lam, rat);
-    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, N, 0, V, Y, T, lz, lam, rat);
+    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, N, 1, V, T, Y, lz, lam, rat);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, N, 0, V, Y, T, lz, lam, rat);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
@@ -759,9 +782,9 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
         return hipGetLastError();
     });
     if (err != hipSuccess) return err;
-    const dim3 grid((ncol + kTN - 1) / kTN, (n + kTM - 1) / kTM, 3);
-    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, P, 1, V, T, Y, lz, lam, rat);
-    hipLaunchKernelGGL((k_col_gemm<R>), grid, dim3(256), 0, s, n, ncol, P, 0, V, Y, T, lz, lam, rat);
+    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, P, 1, V, T, Y, lz, lam, rat);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, P, 0, V, Y, T, lz, lam, rat);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;

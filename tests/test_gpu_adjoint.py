@@ -3,7 +3,7 @@
 * dJ/du and dJ/dtheta of the library equal the oracle's (dense solves,
   five-point differences of its own operator) on a three-element box with a
   cubic coating: 1e-11 relative for dJ/du, 1e-8 for dJ/dtheta.
-* On the coating workload (40 elements, p = 5) the adjoint gradient with
+* On the coating workload (40 elements, p = 5 and 6) the adjoint gradient with
   respect to (Y_coat, nu_coat, Y_sub, nu_sub, coating thickness) equals
   five-point differences of the library's own solve-and-energy pipeline to
   1e-6 (coating 0.05 thick), and obeys Euler's relation
@@ -99,10 +99,13 @@ def gpu_total_energy(spec, rtol=1e-11):
     return float(np.sum(P.energy(u)))
 
 
-def test_coating_gradient_against_differences():
+@pytest.mark.parametrize("p", [5, 6])
+def test_coating_gradient_against_differences(p):
     spec = coating_spec()
-    _, _, _, g = gpu_gradient(spec, COATING_PARAMS, None, rtol=1e-11)
-    for (kind, index), a in zip(COATING_PARAMS, g):
+    spec["p"] = p
+    params = COATING_PARAMS if p == 5 else [("youngs", 1), ("thickness", 0)]
+    _, _, _, g = gpu_gradient(spec, params, None, rtol=1e-11)
+    for (kind, index), a in zip(params, g):
         t0 = adjoint.get_param(spec, kind, index)
         h = 1e-3 * abs(t0)
         f = [gpu_total_energy(dgtn.with_params(spec, [(kind, index)], [t0 + s * h])) for s in (-2, -1, 1, 2)]
