@@ -351,16 +351,17 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     dst[2 * N2] = t[2];
 }
 
+// Six waves per SIMD: with the LDS below that fits three workgroups per CU (FP64,
+// N = 7) at the cost of a few spilled registers; measured faster than two.
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, const R* __restrict__ u,
+__global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, const R* __restrict__ u,
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
-    static_assert(3 * N3 <= 36 * N2, "the eta part of the divergence reuses the lift buffer");
-    __shared__ R su[3 * N3];          // u; later the xi part of the weak divergence
+    __shared__ R su[3 * N3];          // u; later the xi and eta parts of the weak divergence
     __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
-    __shared__ R sLF[6 * 6 * N2];     // per face node: lift into S; later the eta part of the divergence
+    __shared__ R sLF[6 * 3 * N2];     // per face node: lifting factor times the jump
     __shared__ R sw[N];
     __shared__ FaceInfo<R> sface[6];
     __shared__ R sown[4];
@@ -386,9 +387,9 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
     g.hz = sown[3];
     gf.hz = sown[3];
     // neighbour trace and traction of this face node: in flight during the derivatives
-    const FaceInfo<R> fo = sface[fact ? f : 0];
     R un[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
-    if (fact && fo.bc == 0) {
+    if (fact && sface[f].bc == 0) {
+        const FaceInfo<R>& fo = sface[f];
         int i2, j2, k2;
         const Nbr nb{fo.e, fo.f, fo.flip, 0};
         matching_node<N>(f, nb, fi_i, fi_j, fi_k, i2, j2, k2);
@@ -404,13 +405,15 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
     // 1. line lanes: reference derivatives of u
     ref_derivatives<N>(L, su, sG, tid);
     __syncthreads();
-    // 2. node lanes: unlifted gradient and stress; interior traction on each face slot
-    R S[6];
+    // 2. node lanes: unlifted gradient and stress; interior traction on each face slot.
+    // Only this lane reads its node's derivatives, so S is parked in those slots.
     const bool fxi = (i == 0) | (i == N - 1), feta = (j == 0) | (j == N - 1), fzeta = (k == 0) | (k == N - 1);
     if (nact) {
-        R G[3][3], T[6];
+        R G[3][3], T[6], S[6];
         node_gradient<N>(sG, tid, g, G);
         sym_of(G, S);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) sG[q * N3 + tid] = S[q];
         if (fxi | feta | fzeta) {
             cubic_stress(c11, c12, c44, S, T);
             const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
@@ -431,6 +434,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
     __syncthreads();
     // 3. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
     if (fact) {
+        const FaceInfo<R> fo = sface[f];
         R n[3], amag;
         face_normal(f, gf, n, amag);
         R wsig, lr;
@@ -463,24 +467,31 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
             }
         }
         // Neumann faces: no jump and, for homogeneous data, no flux
-        R Sj[6];
-        sym_outer(n, jump, Sj);
 #pragma unroll
-        for (int s = 0; s < 6; ++s) sLF[f * 6 * N2 + s * N2 + fi] = R(-0.5) * lr * Sj[s];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sFT[slot + c * N2] = -wsig * flux[c];
+        for (int c = 0; c < 3; ++c) {
+            sLF[slot + c * N2] = R(-0.5) * lr * jump[c];
+            sFT[slot + c * N2] = -wsig * flux[c];
+        }
     }
     __syncthreads();
     // 4. node lanes: lifted strain, stress and the volume fluxes F^m_c = w J (J^-1)^m_d T^{dc}
     if (nact) {
+        R S[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) S[q] = sG[q * N3 + tid];
         const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
                               fzeta ? (k == 0 ? 4 : 5) : -1};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (faces[q] < 0) continue;
-            const int base = faces[q] * 6 * N2 + face_index<N>(faces[q], i, j, k);
+            const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
+            R n[3], amag, lj[3], Sl[6];
+            face_normal(faces[q], g, n, amag);
 #pragma unroll
-            for (int s = 0; s < 6; ++s) S[s] += sLF[base + s * N2];
+            for (int c = 0; c < 3; ++c) lj[c] = sLF[slot + c * N2];
+            sym_outer(n, lj, Sl);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) S[s] += Sl[s];
         }
         R T[6];
         cubic_stress(c11, c12, c44, S, T);
@@ -497,15 +508,22 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
         }
     }
     __syncthreads();
-    // 5. weak divergence sum_m D_m^T F^m: xi and eta lines into su and sLF ...
-    if (tid < 6 * N2) {
+    // 5. weak divergence sum_m D_m^T F^m: the xi lines write su, the eta lines add to it ...
+    if (tid < 3 * N2) {
         int d, c, base, stride;
         line_of<N>(tid, d, c, base, stride);
-        R* dst = (d == 0 ? su : sLF) + c * N3 + base;
-        line_contract<N, true>(L, sG + (d * 3 + c) * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
+        R* dst = su + c * N3 + base;
+        line_contract<N, true>(L, sG + c * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
     }
     __syncthreads();
-    // ... then the zeta lines add both, and the face fluxes, and write A u
+    if (tid < 3 * N2) {
+        int d, c, base, stride;
+        line_of<N>(tid + 3 * N2, d, c, base, stride);
+        R* dst = su + c * N3 + base;
+        line_contract<N, true>(L, sG + (3 + c) * N3, base, stride, [&](int x, R v) { dst[x * stride] += v; });
+    }
+    __syncthreads();
+    // ... then the zeta lines add theirs and the face fluxes, and write A u
     if (tid < 3 * N2) {
         const int c = tid / N2, q = tid % N2, ii = q % N, jj = q / N;
         R* oe = out + (size_t)e * 3 * N3 + c * N3 + q;
@@ -513,7 +531,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_apply(LevelView<R> L, con
         const R* fy = (jj == 0 || jj == N - 1) ? sFT + (jj == 0 ? 2 : 3) * 3 * N2 + c * N2 + ii : nullptr;
         line_contract<N, true>(L, sG + (6 + c) * N3, q, N2, [&](int x, R v) {
             const int node = x * N2 + q;
-            R r = v + su[c * N3 + node] + sLF[c * N3 + node];
+            R r = v + su[c * N3 + node];
             if (fx) r += fx[x * N];                                   // face_index(xi face) = k * N + j
             if (fy) r += fy[x * N];                                   // face_index(eta face) = k * N + i
             if (x == 0) r += sFT[4 * 3 * N2 + c * N2 + q];            // zeta-: j * N + i
