@@ -322,7 +322,8 @@ __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, con
 // computed on the matrix cores: 16 x 16 x 4 MFMA blocks (FP64 or FP32
 // inputs and accumulation).  A workgroup of four waves owns a 64 x 64 output
 // tile, each wave a 32 x 32 quarter as 2 x 2 blocks; K is staged through LDS in
-// chunks of 16.  Lane l of a block holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// chunks of 32, the next chunk fetched into registers during the products.
+// Lane l of a block holds A[l % 16][l / 16] and B[l / 16][l % 16];
 // its four results are C[row(l, q)][l % 16], q = 0..3, with row = 4 (l / 16) + q
 // for the FP32 instruction and row = 4 q + l / 16 for the FP64 one (measured).
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -339,13 +340,14 @@ template <> struct MfmaAcc<float> {
     __device__ static int row(int lane, int q) { return 4 * (lane / 16) + q; }
 };
 
-constexpr int kGM = 64, kGN = 64, kGK = 16, kGPad = 4;
+constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
 template <typename R>
 __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, int trans, const R* __restrict__ V,
                                                        const R* __restrict__ in, R* __restrict__ out,
                                                        const R* __restrict__ lz, const R* __restrict__ lam,
                                                        const R* __restrict__ rat) {
     using Acc = MfmaAcc<R>;
+    constexpr int LA = kGK * kGM / 256, LB = kGK * kGN / 256;  // staged values per thread
     __shared__ R As[kGK][kGM + kGPad];  // As[k][row]
     __shared__ R Bs[kGK][kGN + kGPad];  // Bs[k][col]
     const int c = blockIdx.z;
@@ -354,27 +356,46 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, i
     const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
     const R* Vc = V + (size_t)c * n * n;
     const R* Bc = in + (size_t)c * n * ncol;
+    // the next K chunk is fetched into registers while the current one is multiplied
+    R ra[LA], rb[LB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < LA; ++t) {
+            const int q = tid + 256 * t;
+            int kk, rr;
+            if (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
+            else { rr = q / kGK; kk = q % kGK; }         // V[row][k]: k contiguous
+            const int kg = k0 + kk, rg = row0 + rr;
+            ra[t] = (kg < n && rg < n) ? (trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg]) : R(0);
+        }
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            const int q = tid + 256 * t;
+            const int kk = q / kGN, cc = q % kGN;
+            const int kg = k0 + kk, cg = col0 + cc;
+            rb[t] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
+        }
+    };
     typename Acc::type acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
+    fetch(0);
     for (int k0 = 0; k0 < n; k0 += kGK) {
-        for (int q = tid; q < kGK * kGM; q += 256) {
-            int kk, rr;
-            if (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
-            else { rr = q / kGK; kk = q % kGK; }         // V[row][k]: k contiguous
-            const int kg = k0 + kk, rg = row0 + rr;
-            R v = 0;
-            if (kg < n && rg < n) v = trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg];
-            As[kk][rr] = v;
+#pragma unroll
+        for (int t = 0; t < LA; ++t) {
+            const int q = tid + 256 * t;
+            if (trans) As[q / kGM][q % kGM] = ra[t];
+            else As[q % kGK][q / kGK] = ra[t];
         }
-        for (int q = tid; q < kGK * kGN; q += 256) {
-            const int kk = q / kGN, cc = q % kGN;
-            const int kg = k0 + kk, cg = col0 + cc;
-            Bs[kk][cc] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            const int q = tid + 256 * t;
+            Bs[q / kGN][q % kGN] = rb[t];
         }
         __syncthreads();
+        if (k0 + kGK < n) fetch(k0 + kGK);
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
             R af[2], bf[2];
