@@ -47,6 +47,8 @@ PROFILE_COMMANDS = {
                   "python3 bench.py --calib-copy",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_write -o run --output-format csv -- "
                   "python3 bench.py --calib-copy",
+    "solve": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/solve -o run --output-format csv -- "
+             "python3 bench.py --one-solve",
 }
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
@@ -185,6 +187,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (HBM-counter calibration)")
+    ap.add_argument("--one-solve", action="store_true",
+                    help="run only one hot-path pass without the apply block (solve + adjoint, rtol 1e-7)")
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="write profiles/ summaries from rocprofv3 output in PROF_DIR and exit")
     args = ap.parse_args()
@@ -199,6 +203,25 @@ def main():
     import torch
     import paper_2111_06893_amd as dgtn
 
+    if args.one_solve:
+        spec = W.config2()
+        P = dgtn.Problem(spec)
+        o = dgtn.default_opts(32, rtol=1e-7)
+        P.bind(o)
+        res = {}
+        for rep in range(2):   # the first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, st = P.solve(opts=o, raise_on_noconv=False)
+            U = P.energy(u)
+            w = np.array([1.0, 0.0])
+            lam, st2 = P.solve(P.energy_grad(u, w), opts=o, raise_on_noconv=False)
+            g = P.grad(u, lam, [("youngs", 1), ("thickness", 0)], w)
+            torch.cuda.synchronize()
+            res = {"seconds": time.perf_counter() - t0, "solve_iters": st.iters, "adjoint_iters": st2.iters,
+                   "U_layers": U.tolist(), "dUcoat": g.tolist()}
+        print(json.dumps(res))
+        return
     if args.calib_copy:
         a = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -363,6 +386,20 @@ def summarize_profiles(prof_dir, commands):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} % |")
     open(os.path.join(out_dir, "kernels_config2_trace.md"), "w").write("\n".join(lines) + "\n")
+    solve_stats = os.path.join(prof_dir, "solve", "run_kernel_stats.csv")
+    if os.path.exists(solve_stats):
+        st = list(csv.DictReader(open(solve_stats)))
+        lines = ["# Kernels of the solve path, thin-coating cylinder (2,058,000 DoF)", "",
+                 "Two passes (the first warms up) of: FP32-preconditioned flexible CG to rtol 1e-7 with the",
+                 "overlapping column-Schwarz preconditioner, layer energies, adjoint solve and parameter",
+                 "derivatives.", "", "Command (from the repository root, TMPDIR=/tmp):", "",
+                 "    " + commands["solve"], "",
+                 "| kernel | calls | average (us) | total (ms) | share |", "|---|---|---|---|---|"]
+        for r in st[:22]:
+            name = r["Name"].replace("dgtn::(anonymous namespace)::", "").replace("void ", "").split("(")[0][:70]
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} % |")
+        open(os.path.join(out_dir, "solve_config2_trace.md"), "w").write("\n".join(lines) + "\n")
 
     copy_bytes = 32 * 2 ** 20 * 8
     cf = [v for k, vs in pmc("copy_fetch", "FETCH_SIZE").items() if "elementwise" in k for v in vs]
