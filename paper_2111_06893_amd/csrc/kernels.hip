@@ -381,11 +381,8 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     const int f = tid / N2, fi = tid % N2;
     int fi_i = 0, fi_j = 0, fi_k = 0;
     if (fact) face_node<N>(f, fi, fi_i, fi_j, fi_k);
-    NodeGeo<R> gf = fact ? node_geo<N>(L, col, iz, fi_i, fi_j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
-    const R sig_side = (fact && f < 4) ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : R(0);
     __syncthreads();
     g.hz = sown[3];
-    gf.hz = sown[3];
     // neighbour trace and traction of this face node: in flight during the derivatives
     R un[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     if (fact && sface[f].bc == 0) {
@@ -434,6 +431,10 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     __syncthreads();
     // 3. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
     if (fact) {
+        // face geometry loaded here rather than held through the earlier phases (register pressure)
+        NodeGeo<R> gf = node_geo<N>(L, col, iz, fi_i, fi_j);
+        gf.hz = sown[3];
+        const R sig_side = f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : R(0);
         const FaceInfo<R> fo = sface[f];
         R n[3], amag;
         face_normal(f, gf, n, amag);
