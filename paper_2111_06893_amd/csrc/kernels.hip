@@ -358,8 +358,8 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
-    __shared__ R su[3 * N3];          // u; later the xi and eta parts of the weak divergence
-    __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F
+    __shared__ R su[3 * N3];          // u
+    __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F, then D^T F
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
     __shared__ R sLF[6 * 3 * N2];     // per face node: lifting factor times the jump
     __shared__ R sw[N];
@@ -509,36 +509,38 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
         }
     }
     __syncthreads();
-    // 5. weak divergence sum_m D_m^T F^m: the xi lines write su, the eta lines add to it ...
-    if (tid < 3 * N2) {
+    // 5. weak divergence sum_m D_m^T F^m, one lane per line: F^m_c along a line is
+    // read by that line's lane only, so each lane overwrites its line in place
+    if (tid < 9 * N2) {
         int d, c, base, stride;
         line_of<N>(tid, d, c, base, stride);
-        R* dst = su + c * N3 + base;
-        line_contract<N, true>(L, sG + c * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
+        R* line = sG + (d * 3 + c) * N3 + base;
+        R v[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) v[a] = line[a * stride];
+#pragma unroll 1
+        for (int x = 0; x < N; ++x) {
+            const R* row = L.Dt + x * N;
+            R acc = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc += row[a] * v[a];
+            line[x * stride] = acc;
+        }
     }
     __syncthreads();
-    if (tid < 3 * N2) {
-        int d, c, base, stride;
-        line_of<N>(tid + 3 * N2, d, c, base, stride);
-        R* dst = su + c * N3 + base;
-        line_contract<N, true>(L, sG + (3 + c) * N3, base, stride, [&](int x, R v) { dst[x * stride] += v; });
-    }
-    __syncthreads();
-    // ... then the zeta lines add theirs and the face fluxes, and write A u
-    if (tid < 3 * N2) {
-        const int c = tid / N2, q = tid % N2, ii = q % N, jj = q / N;
-        R* oe = out + (size_t)e * 3 * N3 + c * N3 + q;
-        const R* fx = (ii == 0 || ii == N - 1) ? sFT + (ii == 0 ? 0 : 1) * 3 * N2 + c * N2 + jj : nullptr;
-        const R* fy = (jj == 0 || jj == N - 1) ? sFT + (jj == 0 ? 2 : 3) * 3 * N2 + c * N2 + ii : nullptr;
-        line_contract<N, true>(L, sG + (6 + c) * N3, q, N2, [&](int x, R v) {
-            const int node = x * N2 + q;
-            R r = v + su[c * N3 + node];
-            if (fx) r += fx[x * N];                                   // face_index(xi face) = k * N + j
-            if (fy) r += fy[x * N];                                   // face_index(eta face) = k * N + i
-            if (x == 0) r += sFT[4 * 3 * N2 + c * N2 + q];            // zeta-: j * N + i
-            if (x == N - 1) r += sFT[5 * 3 * N2 + c * N2 + q];        // zeta+
-            oe[x * N2] = scale * r;
-        });
+    // 6. node lanes: sum of the three directions and the face fluxes, written as A u
+    if (nact) {
+        const int faces[3] = {fxi ? (i == 0 ? 0 : 1) : -1, feta ? (j == 0 ? 2 : 3) : -1,
+                              fzeta ? (k == 0 ? 4 : 5) : -1};
+        R* oe = out + (size_t)e * 3 * N3 + tid;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R r = sG[c * N3 + tid] + sG[(3 + c) * N3 + tid] + sG[(6 + c) * N3 + tid];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (faces[q] >= 0) r += sFT[faces[q] * 3 * N2 + c * N2 + face_index<N>(faces[q], i, j, k)];
+            oe[c * N3] = scale * r;
+        }
     }
 }
 
