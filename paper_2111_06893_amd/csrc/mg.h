@@ -14,9 +14,9 @@ hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, c
                          const R* lz, const R* b, const R* Ax, R* x, R omega, R* T, R* Y, hipStream_t s);
 // overlapping column patches of width P = N + 2k (gather table pg, sum table ps)
 template <typename R>
-hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const int* ps, const R* S,
-                         const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax, R* x,
-                         R omega, R* T, R* Y, hipStream_t s);
+hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const int* ps, const R* wsq,
+                         const R* S, const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax,
+                         R* x, R omega, R* T, R* Y, hipStream_t s);
 template <typename R>
 hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s);
 template <typename R>

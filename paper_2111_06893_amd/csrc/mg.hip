@@ -214,8 +214,9 @@ __global__ __launch_bounds__(nthreads<N>()) void k_col_bwd(int n_cols, int nzN, 
 // T[c][iz*N + k][col*P2 + b'*P + a'] = sum_{a,b} Sx[a][a'] Sy[b][b'] r_patch[c][k][b][a].
 template <int N, typename R>
 __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, const int* __restrict__ pg,
-                                                 const R* __restrict__ S, const R* __restrict__ b,
-                                                 const R* __restrict__ Ax, R* __restrict__ T) {
+                                                 const R* __restrict__ wsq, const R* __restrict__ S,
+                                                 const R* __restrict__ b, const R* __restrict__ Ax,
+                                                 R* __restrict__ T) {
     constexpr int N2 = N * N, N3 = N2 * N;
     extern __shared__ char smem[];
     const int P2 = P * P, NP = 3 * N * P2;
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, con
         R v = 0;
         if (src >= 0) {
             const size_t o = ((size_t)(iz * n_cols + src / N2) * 3 + c) * N3 + k * N2 + src % N2;
-            v = Ax ? b[o] - Ax[o] : b[o];
+            v = (Ax ? b[o] - Ax[o] : b[o]) * wsq[src];
         }
         sr[q] = v;
     }
@@ -292,10 +293,13 @@ __global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, int P, con
 
 // Additive combination: every node sums the patch values of the (up to four)
 // patches that hold it; ps[col][node][4] = patch_col * P2 + position, or -1.
+// wsq = count^(-1/2) of the patches holding each node scales the gather and the
+// sum alike, so the smoother stays symmetric while a node shared by four
+// patches is not over-corrected four times.
 template <int N, typename R>
 __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, const int* __restrict__ ps,
-                                                 const R* __restrict__ T, R* __restrict__ x, R omega,
-                                                 int accumulate) {
+                                                 const R* __restrict__ wsq, const R* __restrict__ T,
+                                                 R* __restrict__ x, R omega, int accumulate) {
     constexpr int N2 = N * N, N3 = N2 * N;
     const size_t tot = (size_t)n_cols * n_z * 3 * N3;
     const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, con
         const int t = tab[q];
         if (t >= 0) acc += row[t];
     }
-    x[o] = (accumulate ? x[o] : R(0)) + omega * acc;
+    x[o] = (accumulate ? x[o] : R(0)) + omega * wsq[(size_t)col * N2 + node] * acc;
 }
 
 // Batched (over the 3 components, blockIdx.z) product along z:
@@ -792,14 +796,14 @@ hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, c
 }
 
 template <typename R>
-hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const int* ps, const R* S,
-                         const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax, R* x,
-                         R omega, R* T, R* Y, hipStream_t s) {
+hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const int* ps, const R* wsq,
+                         const R* S, const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax,
+                         R* x, R omega, R* T, R* Y, hipStream_t s) {
     const int E = n_cols * n_z, n = n_z * N, ncol = n_cols * P * P;
     const size_t shm = sizeof(R) * (size_t)(2 * 3 * N * P * P + 2 * P * P);
     hipError_t err = dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_ovl_fwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, pg, S, b, Ax, T);
+        hipLaunchKernelGGL((k_ovl_fwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, pg, wsq, S, b, Ax, T);
         return hipGetLastError();
     });
     if (err != hipSuccess) return err;
@@ -811,8 +815,8 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
         constexpr int NN = decltype(nn)::value;
         hipLaunchKernelGGL((k_ovl_bwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, S, T);
         const size_t tot = (size_t)E * 3 * NN * NN * NN;
-        hipLaunchKernelGGL((k_ovl_sum<NN, R>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, n_cols, n_z, P, ps, T,
-                           x, omega, Ax ? 1 : 0);
+        hipLaunchKernelGGL((k_ovl_sum<NN, R>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, n_cols, n_z, P, ps, wsq,
+                           T, x, omega, Ax ? 1 : 0);
         return hipGetLastError();
     });
 }
@@ -939,6 +943,7 @@ hipError_t vec_scale_copy(const double* x, double* y, double a, size_t n, hipStr
     template hipError_t mg_col_smooth<R>(int, int, int, const R*, const R*, const R*, const R*,         \
                                          const R*, const R*, const R*, R*, R, R*, R*, hipStream_t);    \
     template hipError_t mg_ovl_smooth<R>(int, int, int, int, const int*, const int*, const R*, const R*, \
+                                         const R*, \
                                          const R*, const R*, const R*, const R*, const R*, R*, R, R*, R*, \
                                          hipStream_t);                                                  \
     template hipError_t mg_prolong_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);           \

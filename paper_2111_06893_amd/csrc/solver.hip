@@ -51,8 +51,9 @@ struct MgLevel {
     int P = 0;
     std::vector<double> cS, clam, crat, cV, clz;
     std::vector<int> pg, ps;
+    std::vector<double> cw;   // [n_cols][N2] count^(-1/2) of the patches holding each node
     size_t off_cS[2] = {0, 0}, off_clam[2] = {0, 0}, off_crat[2] = {0, 0}, off_cV[2] = {0, 0}, off_clz[2] = {0, 0};
-    size_t off_cT[2] = {0, 0}, off_cY[2] = {0, 0}, off_pg = 0, off_ps = 0;
+    size_t off_cT[2] = {0, 0}, off_cY[2] = {0, 0}, off_pg = 0, off_ps = 0, off_cw[2] = {0, 0};
 };
 
 struct SolverState {
@@ -756,6 +757,12 @@ dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts) {
             M.P = cd.P;
             M.pg = std::move(cd.pg);
             M.ps = std::move(cd.ps);
+            M.cw.assign(M.ps.size() / 4, 1.0);
+            for (size_t q = 0; q < M.cw.size(); ++q) {
+                int cnt = 0;
+                for (int t = 0; t < 4; ++t) cnt += M.ps[q * 4 + t] >= 0;
+                M.cw[q] = 1.0 / std::sqrt((double)std::max(cnt, 1));
+            }
             M.cS = std::move(cd.S);
             M.clam = std::move(cd.lam);
             M.crat = std::move(cd.rat);
@@ -795,6 +802,7 @@ void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
                 M.off_pg = lay.take(4 * M.pg.size());
                 M.off_ps = lay.take(4 * M.ps.size());
             }
+            M.off_cw[pi] = lay.take(rs * M.cw.size());
             M.off_x[pi] = lay.take(rs * n);
             M.off_t[pi] = lay.take(rs * n);
         }
@@ -880,6 +888,7 @@ dgtn_status bind_solver(dgtn_ctx* c, hipStream_t s) {
         if (!M.pg.empty()) {
             if ((st = upload(c, M.off_pg, M.pg.data(), 4 * M.pg.size(), s)) != DGTN_OK) return st;
             if ((st = upload(c, M.off_ps, M.ps.data(), 4 * M.ps.size(), s)) != DGTN_OK) return st;
+            if ((st = up2(M.off_cw, M.cw)) != DGTN_OK) return st;
         }
     }
     for (auto& T : S.tr) {
@@ -930,6 +939,7 @@ dgtn_status smooth(dgtn_ctx* c, int l, const VOpts& o, const R* b, const R* Ax, 
     MgLevel& M = S.mg[l];
     if (o.smoother == DGTN_SMOOTH_COLUMN && M.P > L.N) {
         SHIP(mg_ovl_smooth<R>(L.N, L.n_cols, L.n_z, M.P, at<int>(c, M.off_pg), at<int>(c, M.off_ps),
+                              at<R>(c, M.off_cw[pi]),
                               at<R>(c, M.off_cS[pi]), at<R>(c, M.off_clam[pi]), at<R>(c, M.off_crat[pi]),
                               at<R>(c, M.off_cV[pi]), at<R>(c, M.off_clz[pi]), b, Ax, x, (R)o.omega,
                               at<R>(c, M.off_cT[pi]), at<R>(c, M.off_cY[pi]), s));

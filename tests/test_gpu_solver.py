@@ -160,7 +160,7 @@ def test_overlap_on_a_single_column_equals_no_overlap():
     v = _dev(W.random_field(spec, 7))
     out = []
     for ov in (0, 2):
-        o = dgtn.default_opts(64, mg_levels=1, overlap=ov)
+        o = dgtn.default_opts(64, mg_levels=1, smooth_damping=1.0, overlap=ov)
         P.bind(o)
         out.append(P.precondition(v, o).cpu().numpy())
     assert np.max(np.abs(out[0] - out[1])) < 1e-12 * np.max(np.abs(out[0]))
@@ -170,7 +170,7 @@ def test_overlap_on_a_single_column_equals_no_overlap():
 def test_overlapping_preconditioner_is_symmetric_positive(overlap):
     spec = W.config1()
     P = dgtn.Problem(spec)
-    o = dgtn.default_opts(64, mg_levels=1, overlap=overlap)
+    o = dgtn.default_opts(64, mg_levels=1, smooth_damping=1.0, overlap=overlap)
     P.bind(o)
     v = _dev(W.random_field(spec, 1))
     w = _dev(W.random_field(spec, 2))
@@ -187,10 +187,35 @@ def test_overlapping_schwarz_cuts_iterations_and_keeps_the_energy(name):
     P = dgtn.Problem(spec)
     its = {}
     for ov in (0, 1):
-        o = dgtn.default_opts(64, rtol=1e-11, max_iter=20000, overlap=ov)
+        o = dgtn.default_opts(64, rtol=1e-11, max_iter=20000, overlap=ov, mg_levels=1, smooth_damping=1.0)
         P.bind(o)
         u, st = P.solve(opts=o)
         its[ov] = st.iters
         U = P.energy(u)
         np.testing.assert_allclose(U, g["U_layers"], rtol=1e-9)
     assert its[1] * 5 < its[0], its
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_multigrid_with_overlapping_smoother(prec):
+    # default preconditioner: V-cycle over p- and h-coarsened levels, weighted
+    # overlapping column smoother (damping 0.6), dense coarsest solve
+    g = _golden("config1")
+    spec = g["spec"]
+    P = dgtn.Problem(spec)
+    o1 = dgtn.default_opts(prec, rtol=1e-11, max_iter=20000, mg_levels=1, smooth_damping=1.0)
+    P.bind(o1)
+    _, s1 = P.solve(opts=o1)
+    o = dgtn.default_opts(prec, rtol=1e-11, max_iter=20000)
+    P.bind(o)
+    u, st = P.solve(opts=o)
+    np.testing.assert_allclose(P.energy(u), g["U_layers"], rtol=1e-9 if prec == 64 else 1e-8)
+    assert st.iters * 2 < s1.iters, (st.iters, s1.iters)
+    # the V-cycle is a symmetric positive preconditioner
+    v = _dev(W.random_field(spec, 3))
+    w = _dev(W.random_field(spec, 4))
+    Mv, Mw = P.precondition(v, o), P.precondition(w, o)
+    a, b = float(torch.sum(w * Mv)), float(torch.sum(v * Mw))
+    tol = 1e-12 if prec == 64 else 1e-5
+    assert abs(a - b) < tol * float(torch.linalg.norm(v) * torch.linalg.norm(Mw))
+    assert float(torch.sum(v * Mv)) > 0
