@@ -187,9 +187,10 @@ dgtn_status dgtn_rhs(dgtn_ctx* ctx, double* b, hipStream_t stream);
 
 /* Solves A u = b; u holds the initial guess on entry and the solution on
  * exit (device, double).  Returns DGTN_ENOCONV if max_iter is reached or
- * the residual stagnates above rtol (flexible CG losing positive curvature
- * twice without progress of the true residual: rtol below the attainable
- * accuracy); u then holds the last iterate.  DGTN_ENAN on a NaN/Inf. */
+ * the residual stagnates above rtol (flexible CG: no 1 % progress in 200
+ * iterations, or positive curvature lost twice without progress of the true
+ * residual -- rtol below the attainable accuracy); u then holds the last
+ * iterate.  DGTN_ENAN on a NaN/Inf. */
 dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* b,
                        double* u, dgtn_solve_stats* stats, hipStream_t stream);
 

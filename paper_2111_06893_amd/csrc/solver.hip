@@ -1235,6 +1235,9 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         };
         if ((st = start()) != DGTN_OK) return st;
         double breakdown_beta = std::numeric_limits<double>::infinity();
+        double best_beta = std::numeric_limits<double>::infinity();
+        int best_it = 0;
+        const int patience = 200;
         bool have_prev = false;
         int mon_slot[2] = {0, 0};
         while (true) {
@@ -1273,6 +1276,19 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
             if (!std::isfinite(rr)) { set_error("NaN/Inf in the solver"); return DGTN_ENAN; }
             beta = std::sqrt(std::max(rr, 0.0));
             if (verbose && it % 10 == 0) std::fprintf(stderr, "dgtn fcg it %d rel %.3e\n", it, beta / bnorm);
+            // stagnation: no 1 % progress of the residual in `patience` iterations
+            if (beta < 0.99 * best_beta) {
+                best_beta = beta;
+                best_it = it;
+            } else if (it - best_it > patience && beta > target) {
+                SHIP(hipStreamSynchronize(s));
+                if ((st = true_residual(beta)) != DGTN_OK) return st;
+                if (beta <= target) break;
+                why = "stagnated at relative residual " + std::to_string(beta / bnorm) +
+                      " (the attainable accuracy of the FP64 operator)";
+                result = DGTN_ENOCONV;
+                break;
+            }
             if (!broke && beta > target) continue;
             // converged by the recurrence, or lost positive curvature: decide on the
             // FP64 true residual of the current iterate
