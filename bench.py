@@ -234,7 +234,10 @@ def main():
     spec = W.config2()
     n_dof = W.n_dof(spec)
     P = dgtn.Problem(spec)
-    P.bind(dgtn.default_opts(32))
+    if args.no_solve:
+        P.bind()        # operator only: no multigrid hierarchy to set up
+    else:
+        P.bind(dgtn.default_opts(32))
     stream = torch.cuda.current_stream()
     u64 = torch.from_numpy(W.random_field(spec, seed=0)).cuda()
     u32 = u64.float()

@@ -4,10 +4,12 @@
   operators on the same levels (fine p = 3 and coarse p = 1 with the fine
   level's penalty, dense coarse inverse), the library's own Schwarz subdomain
   data and LGL interpolation: FP64 to 1e-10, FP32 to 1e-4.
-* The FP64 solve (flexible CG, column-Schwarz preconditioner) reproduces the
-  oracle's converged layer energies (stored by tests/golden/make_golden.py,
-  which calls only the oracle) to 1e-10 relative; the FP32-preconditioned
-  solve, with the FP64 residual recomputed periodically, to 1e-8.
+* The FP64 solve (flexible CG, multigrid with the overlapping column-Schwarz
+  smoother) reproduces the oracle's converged layer energies (stored by
+  tests/golden/make_golden.py, which calls only the oracle; CG to 1e-13 on the
+  isotropic cylinder, dense direct solves on the thin-coating cases) to 1e-10
+  relative; the FP32-preconditioned solve, with the FP64 residual recomputed
+  periodically, to 1e-8.
 """
 import json
 import os
@@ -104,21 +106,32 @@ def _solve_energy(spec, prec, **kw):
     return P.energy(u), st
 
 
-@pytest.mark.parametrize("name", ["config1", "config3_seed0", "config3_seed1", "config3_seed2"])
+# thin-coating goldens come from dense direct oracle solves; the FP64 residual floor of
+# those operators is near 1e-10, so their solves stop at 1e-9 (the energy error is
+# quadratic in the solution error)
+GOLDEN_CASES = ["config1", "config3_seed0", "config3_seed1", "config3_seed2", "config4_p3_dense",
+                "thin_coating_p3_dense"]
+
+
+def _rtol(name):
+    return 1e-9 if name.endswith("_dense") else 1e-11
+
+
+@pytest.mark.parametrize("name", GOLDEN_CASES)
 def test_fp64_solve_matches_oracle_energy(name):
     g = _golden(name)
     print(f"[solver] fp64 solve {name}", flush=True)
-    U, st = _solve_energy(g["spec"], 64, rtol=1e-11, max_iter=8000)
+    U, st = _solve_energy(g["spec"], 64, rtol=_rtol(name), max_iter=8000)
     ref = np.array(g["U_layers"])
     assert abs(U.sum() / ref.sum() - 1) < 1e-10
     np.testing.assert_allclose(U, ref, rtol=1e-9)
 
 
-@pytest.mark.parametrize("name", ["config1", "config3_seed0", "config3_seed1", "config3_seed2"])
+@pytest.mark.parametrize("name", GOLDEN_CASES)
 def test_mixed_precision_solve_matches_oracle_energy(name):
     g = _golden(name)
     print(f"[solver] fp32-preconditioned solve {name}", flush=True)
-    U, st = _solve_energy(g["spec"], 32, rtol=1e-11, max_iter=8000)
+    U, st = _solve_energy(g["spec"], 32, rtol=_rtol(name), max_iter=8000)
     ref = np.array(g["U_layers"])
     assert abs(U.sum() / ref.sum() - 1) < 1e-8
 
