@@ -32,6 +32,7 @@ def cases():
     tc["p"] = 3
     tc["layers"][1]["n_elem"] = 4
     tc["layers"][1]["ratio"] = 3.0
+    tc["load"]["r0"] = 0.3      # resolved by the 5-column mesh at p = 3
     out["thin_coating_p3_dense"] = tc
     return out
 
