@@ -27,12 +27,16 @@ Thermal-noise data: n_i T_b^{ij} = n^j p(r) on z = 0 with p of eq. laserbeam
 scaled by F0, u_b = 0 on z = H, zero traction on the mantle.
 
 Energy: U = -1/2 int S_ij T^ij dV = 1/2 int D_(i u_j) Y^{ijkl} D_(k u_l) dV with
-the unlifted strain, LGL quadrature, summed per layer.
+the unlifted strain, LGL quadrature, summed per layer; and the same integral
+split by elastic modulus (Sec. 2.1 allows one loss angle per modulus):
+isotropic bulk / shear, cubic c11 / c12 / c44 parts.
 
 Pinned by tests: symmetry, positive definiteness with a Dirichlet face, the
 six-mode rigid-body nullspace, exact reproduction of polynomial and of layered
 stress-continuous solutions, weak = strong on affine meshes, cubic = isotropic,
-O(h^{p+1}) convergence, total force of the load, energy of a uniform strain.
+O(h^{p+1}) convergence, total force of the load, energy of a uniform strain;
+energy parts: they sum to U, closed forms of the parts for uniform dilatation,
+shear and uniaxial strains.
 """
 from __future__ import annotations
 
@@ -274,3 +278,39 @@ def element_blocks(prob):
         e[:, j] = 1.0
         B[:, :, j] = apply(prob, e.reshape(prob.shape), couple=False).reshape(prob.E, nloc)
     return B
+
+
+def _part_tensors(m):
+    """Stiffness tensors of the parts of one material's energy (they sum to Y).
+
+    Sec. 2.1 notes that each independent elastic modulus may carry its own loss
+    angle.  Isotropic (eq. constrel_iso): bulk K d^ij d^kl with K = lambda + 2 mu / 3,
+    and shear mu (d^ik d^jl + d^il d^jk - 2/3 d^ij d^kl).  Cubic (eq.
+    constrel_cryst): the c11, c12 and c44 terms separately.  A third zero part
+    pads the isotropic case."""
+    d = np.eye(3)
+    if m["kind"] == "iso":
+        lam, mu = material.lame(m["Y"], m["nu"])
+        K = lam + 2.0 * mu / 3.0
+        dd = np.einsum("ij,kl->ijkl", d, d)
+        bulk = K * dd
+        shear = mu * (np.einsum("ik,jl->ijkl", d, d) + np.einsum("il,jk->ijkl", d, d) - 2.0 / 3.0 * dd)
+        return [bulk, shear, np.zeros((3, 3, 3, 3))]
+    return [material.cubic(m["c11"], 0.0, 0.0), material.cubic(0.0, m["c12"], 0.0),
+            material.cubic(0.0, 0.0, m["c44"])]
+
+
+def energy_parts(prob, u):
+    """[n_layers, 3]: U_k split by modulus (isotropic: bulk, shear, 0; cubic:
+    c11, c12, c44 parts), each 1/2 sum w J D_(i u_j) Y_part D_(k u_l)."""
+    G = gradient(prob, u)
+    Su = sym(G)
+    wJ = prob.geo.w3[None] * prob.geo.det
+    out = np.zeros((prob.mesh.n_layers, 3))
+    parts = [_part_tensors(m) for m in prob.spec["materials"]]
+    for p in range(3):
+        Yp = np.stack([parts[mi][p] for mi in range(len(parts))])[prob.mesh.mat]
+        dens = np.einsum("eij...,eijkl,ekl...->e...", Su, Yp, Su)
+        per_el = 0.5 * np.sum(wJ * dens, axis=(1, 2, 3))
+        np.add.at(out[:, p], prob.mesh.layer, per_el)
+    return out

@@ -44,3 +44,9 @@ def thin_coating_energy(d, r0, Ys, nus, Yc, nuc, F0=1.0):
     e = (Yc ** 2 * (1 + nus) ** 2 * (1 - 2 * nus) ** 2
          + Ys ** 2 * (1 + nuc) ** 2 * (1 - 2 * nuc)) / (2 * Ys ** 2 * Yc * (1 - nuc ** 2))
     return d * F0 ** 2 * e / (2 * np.pi * r0 ** 2)
+
+
+def noise_psd_parts(U_parts, phi_parts, T, f, F0):
+    """S_x with one loss angle per energy part: W = 2 pi f sum_k,p phi_kp U_kp."""
+    W = float(np.sum(np.asarray(U_parts, float) * np.asarray(phi_parts, float)))
+    return 4.0 * KB * T * W / (np.pi * f * F0 ** 2)
