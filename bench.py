@@ -8,9 +8,9 @@ One timed step is one pass of the whole hot path over the workload: the load
 vector; a block of FP64 operator applications (the DG apply, timed with HIP
 events on the stream it runs on); the FP32-preconditioned flexible-CG solve at
 the stopping tolerance calibrated for a 1e-8 error in the layer energies; the
-energies and S_x; and the adjoint gradient of S_x with respect to (Y_coat,
-nu_coat, Y_sub, nu_sub, coating thickness), i.e. one more solve and the
-parameter derivatives.  The headline value is the DG-apply throughput (DoF x
+energies, S_x (one loss angle per layer, and per bulk / shear part); and the
+adjoint gradient of S_x with respect to (Y_coat, nu_coat, Y_sub, nu_sub,
+coating thickness), i.e. one more solve and the parameter derivatives.  The headline value is the DG-apply throughput (DoF x
 applications / s) of the apply blocks inside the timed steps; the JSON line
 also carries the step breakdown, the FP32 apply rate, time-to-U of the FP64-
 and FP32-preconditioned solves, the roofline of the dominant kernel and the
@@ -262,6 +262,7 @@ def main():
     grad_params = [("youngs", 1), ("poisson", 1), ("youngs", 0), ("poisson", 0), ("thickness", 0)]
     T_K, f_Hz, phi = 300.0, 100.0, np.array([4e-4, 1e-7])   # synthetic loss angles (coating, substrate)
     w_sx = 4 * 1.380649e-23 * T_K * phi / (np.pi * f_Hz * spec["load"]["F0"] ** 2)
+    phi_parts = np.array([[5e-4, 3e-4, 0.0], [1e-7, 1e-7, 0.0]])   # synthetic bulk / shear loss angles
 
     def step():
         """One pass of the hot path; returns (apply block seconds, breakdown)."""
@@ -273,6 +274,8 @@ def main():
             u, st = P.solve(b, opts=opts32, raise_on_noconv=False)
             U = P.energy(u)
             rec["S_x"] = P.noise(U, phi, T_K, f_Hz)
+            parts = P.energy_parts(u)        # bulk / shear split of each isotropic layer
+            rec["S_x_bulk_shear"] = dgtn.noise_psd_parts(parts, phi_parts, T_K, f_Hz, spec["load"]["F0"])
             t1 = time.perf_counter()
             lam, st2 = P.solve(P.energy_grad(u, w_sx), opts=opts32, raise_on_noconv=False)
             rec["dSx_dtheta"] = P.grad(u, lam, grad_params, w_sx).tolist()
@@ -332,6 +335,7 @@ def main():
                  "adjoint_ms": float(np.median([r.get("adjoint_s", 0) for r in recs])) * 1e3,
                  "solve_iters": recs[-1].get("solve_iters"), "adjoint_iters": recs[-1].get("adjoint_iters"),
                  "U_layers": recs[-1].get("U_layers"), "S_x": recs[-1].get("S_x"),
+                 "S_x_bulk_shear": recs[-1].get("S_x_bulk_shear"),
                  "dSx_dtheta": recs[-1].get("dSx_dtheta"),
                  "theta": ["Y_coat", "nu_coat", "Y_sub", "nu_sub", "d_coat"]},
         "apply_fp64_us": a64 * 1e6,

@@ -241,6 +241,22 @@ dgtn_status dgtn_energy_grad(dgtn_ctx* ctx, const double* u, const double* w_lay
 dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const double* w_layers,
                       int n_params, const dgtn_param* params, double* dJ, hipStream_t stream);
 
+/* The layer energies split by elastic modulus, the decomposition Sec. 2.1
+ * notes for materials whose independent moduli carry their own loss angles:
+ * parts[3 k + q] for layer k is, for an isotropic layer (eq. constrel_iso),
+ * q = 0 the bulk part 1/2 int K (tr S)^2 with K = lambda + 2 mu / 3, q = 1 the
+ * shear part (the rest), q = 2 zero; for a cubic layer (eq. constrel_cryst)
+ * the parts carried by c11, c12 and c44.  The parts of a layer sum to its
+ * energy of dgtn_energy.  u: device double, n_dof; parts: host, 3 n_layers (J).
+ * Synchronises the stream. */
+dgtn_status dgtn_energy_parts(dgtn_ctx* ctx, const double* u, double* parts, hipStream_t stream);
+
+/* S_x = 4 kB T sum_{k,q} phi[3 k + q] parts[3 k + q] / (pi f F0^2): the noise
+ * with one loss angle per energy part of dgtn_energy_parts.  Pure host
+ * function; DGTN_EINVAL for n_layers < 1, T <= 0, f <= 0 or F0 = 0. */
+dgtn_status dgtn_noise_psd_parts(const double* parts, const double* phi, int n_layers, double T, double f,
+                                 double F0, double* S_x);
+
 /* Thermal-noise power spectral density from the layer energies:
  * S_x = 4 kB T sum_k phi_k U_k / (pi f F0^2), the reading of eqs.
  * thermalnoise / wdiss in which the dissipated power is 2 pi f U phi.  Pure

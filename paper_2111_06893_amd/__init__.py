@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import DgtnError, check, load
 
-__all__ = ["Problem", "DgtnError", "noise_psd", "load", "problem_struct", "default_opts", "PARAM_KINDS",
+__all__ = ["Problem", "DgtnError", "noise_psd", "noise_psd_parts", "load", "problem_struct", "default_opts", "PARAM_KINDS",
            "with_params", "EnergyFn", "layer_energies"]
 
 # Parameter kinds of the energy gradient (dgtn_param.kind)
@@ -81,6 +81,20 @@ def with_params(spec, params, values):
         else:
             raise ValueError(f"unknown parameter kind {kind!r}")
     return s
+
+
+def noise_psd_parts(U_parts, phi_parts, T, f, F0):
+    """S_x with one loss angle per energy part (arrays [n_layers, 3])."""
+    lib = load()
+    U = np.ascontiguousarray(U_parts, dtype=np.float64)
+    ph = np.ascontiguousarray(phi_parts, dtype=np.float64)
+    if U.shape != ph.shape or U.ndim != 2 or U.shape[1] != 3:
+        raise ValueError("expected [n_layers, 3] energy parts and loss angles")
+    out = ctypes.c_double()
+    check(lib.dgtn_noise_psd_parts(U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), U.shape[0], T, f, F0,
+                                   ctypes.byref(out)))
+    return out.value
 
 
 def default_opts(precision=64, **kw):
@@ -217,6 +231,17 @@ class Problem:
         out = np.zeros(self.n_layers)
         check(self.lib.dgtn_energy(self.ctx, ctypes.c_void_p(u.data_ptr()),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
+        return out
+
+    def energy_parts(self, u):
+        """[n_layers, 3] layer energies split by modulus (isotropic: bulk, shear, 0;
+        cubic: c11, c12, c44 parts), numpy, J."""
+        import torch
+        self._ensure()
+        self._check_field(u, torch.float64)
+        out = np.zeros((self.n_layers, 3))
+        check(self.lib.dgtn_energy_parts(self.ctx, ctypes.c_void_p(u.data_ptr()),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
         return out
 
     def energy_grad(self, u, w_layers=None):

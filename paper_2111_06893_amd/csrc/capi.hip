@@ -84,6 +84,7 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
         L.off_xy = lay.take(8 * (size_t)L.n_cols * 2 * N2);
     }
     c->off_Ue = lay.take(8 * (size_t)c->levels[0].E);
+    c->off_abc = lay.take(8 * 3 * (size_t)c->levels[0].E);
     plan_adjoint(c, lay);
     plan_solver(c, opts, lay);
 }
@@ -334,6 +335,54 @@ dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, hipStrea
     }
     for (int k = 0; k < nl; ++k)
         if (!std::isfinite(U_layers[k])) { set_error("non-finite energy"); return DGTN_ENAN; }
+    return DGTN_OK;
+}
+
+dgtn_status dgtn_energy_parts(dgtn_ctx* c, const double* u, double* parts, hipStream_t s) {
+    if (!c || !u || !parts) { set_error("null argument"); return DGTN_EINVAL; }
+    if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
+    const Level& L = c->levels[0];
+    auto v = view_of<double>(c, L);
+    double* abc = reinterpret_cast<double*>(c->ws + c->off_abc);
+    HIP_CHECK(launch_energy_invariants(v, u, abc, s));
+    std::vector<double> h((size_t)3 * L.E);
+    HIP_CHECK(hipMemcpyAsync(h.data(), abc, 8 * h.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    const int nl = (int)c->prob.layers.size();
+    std::vector<double> inv((size_t)3 * nl, 0.0);
+    for (int e = 0; e < L.E; ++e) {  // fixed order: deterministic
+        const int k = L.zlayer[e / L.n_cols];
+        for (int q = 0; q < 3; ++q) inv[(size_t)3 * k + q] += h[(size_t)3 * e + q];
+    }
+    for (int k = 0; k < nl; ++k) {
+        const int m = c->prob.layers[k].material;
+        const double c11 = c->matc[3 * m], c12 = c->matc[3 * m + 1], c44 = c->matc[3 * m + 2];
+        const double A = inv[3 * k], B = inv[3 * k + 1], C = inv[3 * k + 2];
+        double* out = parts + 3 * k;
+        if (c->prob.materials[m].kind == DGTN_MAT_ISO) {
+            const double K = (c11 + 2.0 * c12) / 3.0;  // lambda + 2 mu / 3
+            out[0] = K * (A + B);
+            out[1] = c11 * A + c12 * B + c44 * C - out[0];
+            out[2] = 0.0;
+        } else {
+            out[0] = c11 * A;
+            out[1] = c12 * B;
+            out[2] = c44 * C;
+        }
+        for (int q = 0; q < 3; ++q)
+            if (!std::isfinite(out[q])) { set_error("non-finite energy"); return DGTN_ENAN; }
+    }
+    return DGTN_OK;
+}
+
+dgtn_status dgtn_noise_psd_parts(const double* parts, const double* phi, int n_layers, double T, double f, double F0,
+                                 double* S) {
+    if (!parts || !phi || !S || n_layers < 1) { set_error("invalid argument"); return DGTN_EINVAL; }
+    if (!(T > 0) || !(f > 0) || !(F0 != 0)) { set_error("T, f must be > 0 and F0 != 0"); return DGTN_EINVAL; }
+    const double kB = 1.380649e-23;
+    double W = 0;
+    for (int q = 0; q < 3 * n_layers; ++q) W += phi[q] * parts[q];
+    *S = 4.0 * kB * T * W / (M_PI * f * F0 * F0);
     return DGTN_OK;
 }
 

@@ -37,7 +37,7 @@ struct dgtn_ctx {
     bool bound = false;
     dgtn_solve_opts bound_opts{};
     bool has_opts = false;
-    size_t off_Ue = 0;
+    size_t off_Ue = 0, off_abc = 0;
     dgtn::AdjointLayout adj;
     std::vector<std::vector<char>> staging;  // host staging of FP32 uploads
     dgtn::SolverState* solver = nullptr;
@@ -59,6 +59,7 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
                       double* b, hipStream_t s);
 template <typename R>
 hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s);
+hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s);
 hipError_t launch_energy_grad(const LevelView<double>& L, const double* u, const double* wz, double* g, double scale,
                               hipStream_t s);
 template <>

@@ -623,6 +623,64 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<R> L, con
     if (tid == 0) Ue[e] = red[0];
 }
 
+// Per element, the three quadrature sums from which every per-modulus part of the
+// energy follows (the moduli are applied on the host):
+//   A = 1/2 int sum_i S_ii^2,   B = int sum_{i<j} S_ii S_jj,   C = 2 int sum_{i<j} S_ij^2,
+// so that U = c11 A + c12 B + c44 C and the bulk part is K (A + B).
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy_invariants(LevelView<double> L,
+                                                                      const double* __restrict__ u,
+                                                                      double* __restrict__ abc) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = threads_for<N>();
+    __shared__ double su[3 * N3];
+    __shared__ double sD[N2];
+    __shared__ double red[3][NT];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    __syncthreads();
+    double a = 0, b = 0, c = 0;
+    if (tid < N3) {
+        const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+        const int col = e % L.n_cols, iz = e / L.n_cols;
+        const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
+        double G[3][3], S[6];
+        gradient<N>(su, sD, i, j, k, g, G);
+        sym_of(G, S);
+        const double wJ = L.w[i] * L.w[j] * L.w[k] * g.det2 * 0.5 * g.hz;
+        a = wJ * 0.5 * (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+        b = wJ * (S[0] * S[1] + S[1] * S[2] + S[0] * S[2]);
+        c = wJ * 2.0 * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
+    }
+    red[0][tid] = a;
+    red[1][tid] = b;
+    red[2][tid] = c;
+    __syncthreads();
+    if (tid < 64) {  // fixed-order reduction
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int q = tid; q < NT; q += 64) {
+            s0 += red[0][q];
+            s1 += red[1][q];
+            s2 += red[2][q];
+        }
+        red[0][tid] = s0;
+        red[1][tid] = s1;
+        red[2][tid] = s2;
+    }
+    __syncthreads();
+    for (int st = 32; st > 0; st >>= 1) {
+        if (tid < st) {
+            red[0][tid] += red[0][tid + st];
+            red[1][tid] += red[1][tid + st];
+            red[2][tid] += red[2][tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid < 3) abc[(size_t)e * 3 + tid] = red[tid][0];
+}
+
 // g = scale * w(layer) * sum_m Dhat_m^T [w J (J^-1)^m_i Y^{ijkl} D_(k u_l)]: the
 // derivative with respect to u of the layer-weighted energy sum_k w_k U_k.
 template <int N>
@@ -724,6 +782,14 @@ hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStrea
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         hipLaunchKernelGGL((k_energy<NN, R>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy_invariants<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, abc);
         return hipGetLastError();
     });
 }

@@ -107,6 +107,24 @@ def test_rhs_and_energy_match_oracle(name):
     np.testing.assert_allclose(U, Uref, rtol=1e-12)
 
 
+@pytest.mark.parametrize("name", ["config1", "cyl_refine0_p4_cubic", "box_p2_pressure_sides"])
+def test_energy_parts_match_oracle(name):
+    spec = CASES[name]
+    print(f"[parity] energy parts {name}", flush=True)
+    P = dgtn.Problem(spec)
+    O = dg.Problem(spec)
+    u = W.random_field(spec, seed=21) * 1e-9
+    parts = P.energy_parts(_dev(u))
+    ref = dg.energy_parts(O, u)
+    scale = np.abs(ref).sum(axis=1, keepdims=True)
+    assert np.max(np.abs(parts - ref) / scale) < 1e-12
+    np.testing.assert_allclose(parts.sum(axis=1), P.energy(_dev(u)), rtol=1e-12)
+    phi = np.array([[1e-4, 3e-4, 2e-4]] * parts.shape[0])
+    from oracle import physics
+    sx = dgtn.noise_psd_parts(parts, phi, 290.0, 50.0, spec["load"]["F0"])
+    assert sx == pytest.approx(physics.noise_psd_parts(ref, phi, 290.0, 50.0, spec["load"]["F0"]), rel=1e-12)
+
+
 def test_rigid_modes_in_nullspace_all_neumann():
     spec = CASES["box_p7_free"]
     P = dgtn.Problem(spec)
