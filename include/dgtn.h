@@ -119,7 +119,11 @@ typedef struct {
     int restart;              /* FGMRES restart length m (1..200)              */
     int max_iter;             /* total iteration cap                           */
     double rtol;              /* stop at ||b - A u|| <= rtol ||b||             */
-    int mg_levels;            /* levels of the V-cycle (1 = smoother only)      */
+    int mg_levels;            /* at most this many V-cycle levels (1 = smoother
+                                 only): degree halved to 1, then 2 x 2 columns
+                                 merged, then z-element pairs merged into
+                                 fiducial layers while the coarsest level has
+                                 more than 4096 unknowns                       */
     int smooth_steps;         /* pre- and post-smoothing sweeps per level       */
     double smooth_damping;    /* damping of the additive Schwarz smoother      */
     int smoother;             /* Schwarz subdomains: DGTN_SMOOTH_ELEMENT or DGTN_SMOOTH_COLUMN */

@@ -65,7 +65,6 @@ template float* tau_of<float>(const dgtn_ctx*, const Level&);
 // buffers, energy scratch, and the solver's vectors for `opts`.
 static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
     lay.cursor = 0;
-    const int nmat = (int)c->prob.materials.size();
     for (auto& L : c->levels) {
         const size_t N = L.N, N2 = N * N;
         for (int pi = 0; pi < 2; ++pi) {
@@ -73,7 +72,7 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
             L.off_geo2[pi] = lay.take(rs * L.n_cols * 5 * N2);
             L.off_sig[pi] = lay.take(rs * L.n_cols * 4 * N);
             L.off_hz[pi] = lay.take(rs * L.n_z);
-            L.off_mat[pi] = lay.take(rs * nmat * 3);
+            L.off_mat[pi] = lay.take(rs * level_mat(c, L).size());
             L.off_D[pi] = lay.take(rs * N2);
             L.off_w[pi] = lay.take(rs * N);
             L.off_tau[pi] = lay.take(rs * (size_t)L.E * 6 * 3 * N2);
@@ -235,8 +234,6 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
         c->has_opts = opts != nullptr;
         // upload geometry, FP64 and FP32 mirrors
         const double yr = c->y_ref;
-        std::vector<double> matn(c->matc.size());
-        for (size_t i = 0; i < matn.size(); ++i) matn[i] = c->matc[i] / yr;
         c->staging.clear();
         auto put64 = [&](size_t off, const std::vector<double>& v) -> hipError_t {
             return hipMemcpyAsync(c->ws + off, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
@@ -258,6 +255,8 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
             HIP_CHECK(put32(L.off_sig[1], L.sig_side));
             HIP_CHECK(put64(L.off_hz[0], L.hz));
             HIP_CHECK(put32(L.off_hz[1], L.hz));
+            std::vector<double> matn(level_mat(c, L));
+            for (auto& v : matn) v /= yr;
             HIP_CHECK(put64(L.off_mat[0], matn));
             HIP_CHECK(put32(L.off_mat[1], matn));
             HIP_CHECK(put64(L.off_D[0], L.lgl.D));

@@ -46,6 +46,11 @@ struct dgtn_ctx {
 
 namespace dgtn {
 
+// materials of a level (the problem's own unless the level merged layers)
+inline const std::vector<double>& level_mat(const dgtn_ctx* c, const Level& L) {
+    return L.mat.empty() ? c->matc : L.mat;
+}
+
 template <typename R>
 LevelView<R> view_of(const dgtn_ctx* c, const Level& L);
 template <typename R>

@@ -53,6 +53,9 @@ struct Level {
     std::vector<int> cnbr, cnf;
     std::vector<double> hz, ztop;
     std::vector<int> zmat, zlayer;
+    // c11, c12, c44 (Pa) of the materials zmat indexes on this level; empty on levels
+    // that use the problem's own materials (z-coarsened levels add effective ones)
+    std::vector<double> mat;
     // workspace offsets (bytes) of the uploaded arrays, FP64 and FP32 mirrors
     size_t off_geo2[2], off_sig[2], off_hz[2], off_mat[2], off_D[2], off_w[2];
     size_t off_cnbr, off_cnf, off_zmat, off_xy;

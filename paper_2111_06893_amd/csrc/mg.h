@@ -18,6 +18,10 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
                          const R* S, const R* lam, const R* rat, const R* V, const R* lz, const R* b, const R* Ax,
                          R* x, R omega, R* T, R* Y, hipStream_t s);
 template <typename R>
+hipError_t mg_prolong_z(int N, int Ef, int n_cols, const int* zpar, const R* Iz, const R* uc, R* uf, hipStream_t s);
+template <typename R>
+hipError_t mg_restrict_z(int N, int Ec, int n_cols, const int* zch, const R* Iz, const R* rf, R* rc, hipStream_t s);
+template <typename R>
 hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s);
 template <typename R>
 hipError_t mg_restrict_p(int E, int Nf, int Nc, const R* I, const R* rf, R* rc, hipStream_t s);

@@ -9,6 +9,8 @@
 //                   Lagrange interpolation between LGL grids, and its transpose).
 //  * k_prolong_h / k_restrict_h   transfers between a column and its 2 x 2
 //                   children (z unchanged).
+//  * k_prolong_z / k_restrict_z   transfers between pairs of z-elements and
+//                   their merged (fiducial-layer) element.
 //  * dense coarse solve: Gauss-Jordan inversion steps and a matrix-vector product.
 //  * vector algebra for FGMRES: fused multi-dot, multi-axpy, casts.
 #include <hip/hip_runtime.h>
@@ -534,6 +536,47 @@ __global__ void k_prolong_h(int N, int ncf, int ncc, const int* __restrict__ par
     }
 }
 
+// Transfers between a level and its z-coarsened level (each column's z-elements
+// merged in pairs; an unpaired last element is carried over).  Iz[izf][k][kk] is
+// coarse basis function kk at node k of fine z-element izf, zpar[izf] its coarse
+// element, zch[izc][2] the fine elements of coarse element izc (-1 if none).
+template <typename R>
+__global__ void k_prolong_z(int N, int n_cols, const int* __restrict__ zpar, const R* __restrict__ Iz,
+                            const R* __restrict__ uc, R* __restrict__ uf) {
+    const int ef = blockIdx.x, tid = threadIdx.x;
+    const int col = ef % n_cols, izf = ef / n_cols;
+    const size_t ec = (size_t)zpar[izf] * n_cols + col;
+    const int N2 = N * N, N3 = N2 * N;
+    const R* I = Iz + (size_t)izf * N2;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) {
+        const int ij = q % N2, k = (q / N2) % N, c = q / N3;
+        const R* src = uc + ec * 3 * N3 + c * N3 + ij;
+        R acc = 0;
+        for (int kk = 0; kk < N; ++kk) acc += I[k * N + kk] * src[kk * N2];
+        uf[(size_t)ef * 3 * N3 + q] += acc;
+    }
+}
+
+template <typename R>
+__global__ void k_restrict_z(int N, int n_cols, const int* __restrict__ zch, const R* __restrict__ Iz,
+                             const R* __restrict__ rf, R* __restrict__ rc) {
+    const int ec = blockIdx.x, tid = threadIdx.x;
+    const int col = ec % n_cols, izc = ec / n_cols;
+    const int N2 = N * N, N3 = N2 * N;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) {
+        const int ij = q % N2, kk = (q / N2) % N, c = q / N3;
+        R acc = 0;
+        for (int s = 0; s < 2; ++s) {
+            const int izf = zch[izc * 2 + s];
+            if (izf < 0) continue;
+            const R* I = Iz + (size_t)izf * N2;
+            const R* src = rf + ((size_t)izf * n_cols + col) * 3 * N3 + c * N3 + ij;
+            for (int k = 0; k < N; ++k) acc += I[k * N + kk] * src[k * N2];
+        }
+        rc[(size_t)ec * 3 * N3 + q] = acc;
+    }
+}
+
 template <typename R>
 __global__ void k_restrict_h(int N, int ncf, int ncc, const int* __restrict__ children,
                              const R* __restrict__ Ih, const R* __restrict__ rf, R* __restrict__ rc) {
@@ -822,6 +865,18 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
 }
 
 template <typename R>
+hipError_t mg_prolong_z(int N, int Ef, int n_cols, const int* zpar, const R* Iz, const R* uc, R* uf, hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong_z<R>), dim3(Ef), dim3(256), 0, s, N, n_cols, zpar, Iz, uc, uf);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t mg_restrict_z(int N, int Ec, int n_cols, const int* zch, const R* Iz, const R* rf, R* rc, hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict_z<R>), dim3(Ec), dim3(256), 0, s, N, n_cols, zch, Iz, rf, rc);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s) {
     hipLaunchKernelGGL((k_prolong_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, uc, uf);
     return hipGetLastError();
@@ -946,6 +1001,8 @@ hipError_t vec_scale_copy(const double* x, double* y, double a, size_t n, hipStr
                                          const R*, \
                                          const R*, const R*, const R*, const R*, const R*, R*, R, R*, R*, \
                                          hipStream_t);                                                  \
+    template hipError_t mg_prolong_z<R>(int, int, int, const int*, const R*, const R*, R*, hipStream_t); \
+    template hipError_t mg_restrict_z<R>(int, int, int, const int*, const R*, const R*, R*, hipStream_t); \
     template hipError_t mg_prolong_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);           \
     template hipError_t mg_restrict_p<R>(int, int, int, const R*, const R*, R*, hipStream_t);          \
     template hipError_t mg_prolong_h<R>(int, int, int, int, const int*, const int*, const R*, const R*, \

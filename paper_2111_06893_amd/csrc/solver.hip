@@ -36,10 +36,11 @@ namespace dgtn {
 constexpr int kMaxDenseCoarse = 16384;
 
 struct Transfer {
-    int type = 0;  // 0: degree, 1: columns (2 x 2 children)
+    int type = 0;  // 0: degree, 1: columns (2 x 2 children), 2: z-element pairs
     std::vector<double> I;
     std::vector<int> parent, child, children;
-    size_t off_I[2] = {0, 0}, off_parent = 0, off_child = 0, off_children = 0;
+    std::vector<int> zpar, zch;  // type 2: coarse z of each fine z; fine z pair of each coarse z
+    size_t off_I[2] = {0, 0}, off_parent = 0, off_child = 0, off_children = 0, off_zpar = 0, off_zch = 0;
 };
 
 struct MgLevel {
@@ -183,10 +184,11 @@ void build_fdm(const dgtn_ctx* c, const Level& L, std::vector<double>& out) {
     out.assign((size_t)L.E * 9 * PER, 0.0);
     const double yr = c->y_ref;
     const double cn2 = L.pen_z;
+    const std::vector<double>& mc = level_mat(c, L);
     auto consts = [&](int m, double& c11, double& c12, double& c44) {
-        c11 = c->matc[3 * m] / yr;
-        c12 = c->matc[3 * m + 1] / yr;
-        c44 = c->matc[3 * m + 2] / yr;
+        c11 = mc[3 * m] / yr;
+        c12 = mc[3 * m + 1] / yr;
+        c44 = mc[3 * m + 2] / yr;
     };
     for (int col = 0; col < L.n_cols; ++col) {
         const double* gg = &L.geo2[(size_t)col * 5 * N2];
@@ -648,7 +650,7 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
     std::vector<double> ms(n);
     for (int e = 0; e < nz; ++e)
         for (int k = 0; k < N; ++k)
-            ms[e * N + k] = 1.0 / std::sqrt(c->matc[3 * L.zmat[e] + 2] / yr * L.lgl.w[k] * 0.5 * L.hz[e]);
+            ms[e * N + k] = 1.0 / std::sqrt(level_mat(c, L)[3 * L.zmat[e] + 2] / yr * L.lgl.w[k] * 0.5 * L.hz[e]);
     for (int cc = 0; cc < 3; ++cc) {
         if (cc == 1) {  // same modulus along z as component 0
             std::copy(out.V.begin(), out.V.begin() + (size_t)n * n, out.V.begin() + (size_t)n * n);
@@ -656,7 +658,7 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
             continue;
         }
         std::vector<double> kap(nz);
-        for (int e = 0; e < nz; ++e) kap[e] = c->matc[3 * L.zmat[e] + (cc == 2 ? 0 : 2)] / yr;
+        for (int e = 0; e < nz; ++e) kap[e] = level_mat(c, L)[3 * L.zmat[e] + (cc == 2 ? 0 : 2)] / yr;
         auto K = column_1d(L.lgl, L.hz, kap, L.pen_z, c->prob.bc_top, c->prob.bc_bottom);
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) K[(size_t)i * n + j] *= ms[i] * ms[j];
@@ -673,7 +675,75 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
 
 // ---- level hierarchy -----------------------------------------------------------
 
+// The level with each column's z-elements merged in pairs (an unpaired last one
+// kept): fiducial layers whose material, where the pair mixes two, is the
+// thickness-weighted average of the two stiffness constants.  Columns, degree and
+// side geometry are those of F.
+// z-coarsening stops once the coarsest level has at most this many unknowns
+constexpr size_t kCoarseTarget = 4096;
+
+Level zcoarsen(const dgtn_ctx* c, const Level& F) {
+    Level C = F;
+    C.mat = level_mat(c, F);
+    C.hz.clear();
+    C.ztop.clear();
+    C.zmat.clear();
+    C.zlayer.clear();
+    for (int a = 0; a < F.n_z; a += 2) {
+        const int b = a + 1;
+        if (b >= F.n_z) {
+            C.hz.push_back(F.hz[a]);
+            C.ztop.push_back(F.ztop[a]);
+            C.zmat.push_back(F.zmat[a]);
+            C.zlayer.push_back(F.zlayer[a]);
+            continue;
+        }
+        const double H = F.hz[a] + F.hz[b];
+        C.hz.push_back(H);
+        C.ztop.push_back(F.ztop[a]);
+        C.zlayer.push_back(F.zlayer[a]);
+        if (F.zmat[a] == F.zmat[b]) {
+            C.zmat.push_back(F.zmat[a]);
+            continue;
+        }
+        const std::vector<double>& fm = level_mat(c, F);
+        for (int q = 0; q < 3; ++q)
+            C.mat.push_back((F.hz[a] * fm[3 * F.zmat[a] + q] + F.hz[b] * fm[3 * F.zmat[b] + q]) / H);
+        C.zmat.push_back((int)C.mat.size() / 3 - 1);
+    }
+    C.n_z = (int)C.hz.size();
+    C.E = C.n_z * C.n_cols;
+    return C;
+}
+
 void build_transfer(const dgtn_ctx* c, const Level& F, const Level& C, Transfer& T) {
+    if (F.N == C.N && F.n_cols == C.n_cols && F.n_z != C.n_z) {
+        // z-element pairs: fine element a (upper) and b of coarse element m; the
+        // fine nodes sit at coarse coordinates split in proportion to the widths
+        T.type = 2;
+        const int N = F.N, N2 = N * N;
+        T.I.assign((size_t)F.n_z * N2, 0.0);
+        T.zpar.assign(F.n_z, -1);
+        T.zch.assign((size_t)C.n_z * 2, -1);
+        for (int m = 0; m < C.n_z; ++m) {
+            const int a = 2 * m, b = 2 * m + 1;
+            const bool pair = b < F.n_z;
+            const double ha = F.hz[a], hb = pair ? F.hz[b] : 0.0, H = ha + hb;
+            for (int half = 0; half < (pair ? 2 : 1); ++half) {
+                const int f = a + half;
+                std::vector<double> y(N);
+                for (int k = 0; k < N; ++k) {
+                    const double t = 0.5 * (F.lgl.x[k] + 1.0);  // position within the fine element
+                    y[k] = half == 0 ? -1.0 + 2.0 * ha * t / H : -1.0 + 2.0 * (ha + hb * t) / H;
+                }
+                auto M = lagrange_matrix(C.lgl, y);
+                std::copy(M.begin(), M.end(), T.I.begin() + (size_t)f * N2);
+                T.zpar[f] = m;
+                T.zch[(size_t)m * 2 + half] = f;
+            }
+        }
+        return;
+    }
     if (F.N != C.N) {
         T.type = 0;
         T.I = lagrange_matrix(C.lgl, F.lgl.x);  // [Nf][Nc]
@@ -743,7 +813,11 @@ dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts) {
     while ((int)c->levels.size() < want) {
         if (p > 1) p = std::max(1, p / 2);
         else if (r > 0) --r;
-        else break;
+        else if (c->levels.back().n_z > 2 && ndof(c->levels.back()) > kCoarseTarget) {
+            // then merge layers into fiducial ones until the coarsest solve is small
+            c->levels.push_back(zcoarsen(c, c->levels.back()));
+            continue;
+        } else break;
         c->levels.push_back(build_level(c->prob, p, r, c->levels[0].N - 1, c->levels[0].refine));
     }
     S.mg.assign(c->levels.size(), MgLevel{});
@@ -813,6 +887,9 @@ void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
             T.off_parent = lay.take(4 * T.parent.size());
             T.off_child = lay.take(4 * T.child.size());
             T.off_children = lay.take(4 * T.children.size());
+        } else if (T.type == 2) {
+            T.off_zpar = lay.take(4 * T.zpar.size());
+            T.off_zch = lay.take(4 * T.zch.size());
         }
     }
     if (S.dense) {
@@ -898,6 +975,9 @@ dgtn_status bind_solver(dgtn_ctx* c, hipStream_t s) {
             if ((st = upload(c, T.off_parent, T.parent.data(), 4 * T.parent.size(), s)) != DGTN_OK) return st;
             if ((st = upload(c, T.off_child, T.child.data(), 4 * T.child.size(), s)) != DGTN_OK) return st;
             if ((st = upload(c, T.off_children, T.children.data(), 4 * T.children.size(), s)) != DGTN_OK) return st;
+        } else if (T.type == 2) {
+            if ((st = upload(c, T.off_zpar, T.zpar.data(), 4 * T.zpar.size(), s)) != DGTN_OK) return st;
+            if ((st = upload(c, T.off_zch, T.zch.data(), 4 * T.zch.size(), s)) != DGTN_OK) return st;
         }
     }
     SHIP(hipStreamSynchronize(s));
@@ -990,10 +1070,12 @@ dgtn_status vcycle(dgtn_ctx* c, int l, const VOpts& o, hipStream_t s) {
     R* xc = at<R>(c, MC.off_x[pi]);
     const R* I = at<R>(c, T.off_I[pi]);
     if (T.type == 0) SHIP(mg_restrict_p<R>(L.E, L.N, C.N, I, t, bc, s));
+    else if (T.type == 2) SHIP(mg_restrict_z<R>(L.N, C.E, L.n_cols, at<int>(c, T.off_zch), I, t, bc, s));
     else SHIP(mg_restrict_h<R>(L.N, C.E, L.n_cols, C.n_cols, at<int>(c, T.off_children), I, t, bc, s));
     st = vcycle<R>(c, l + 1, o, s);
     if (st != DGTN_OK) return st;
     if (T.type == 0) SHIP(mg_prolong_p<R>(L.E, L.N, C.N, I, xc, x, s));
+    else if (T.type == 2) SHIP(mg_prolong_z<R>(L.N, L.E, L.n_cols, at<int>(c, T.off_zpar), I, xc, x, s));
     else
         SHIP(mg_prolong_h<R>(L.N, L.E, L.n_cols, C.n_cols, at<int>(c, T.off_parent), at<int>(c, T.off_child), I, xc,
                              x, s));
@@ -1284,8 +1366,10 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
                 SHIP(hipStreamSynchronize(s));
                 if ((st = true_residual(beta)) != DGTN_OK) return st;
                 if (beta <= target) break;
-                why = "stagnated at relative residual " + std::to_string(beta / bnorm) +
-                      " (the attainable accuracy of the FP64 operator)";
+                char msg[128];
+                std::snprintf(msg, sizeof msg, "stagnated at relative residual %.3e (the attainable accuracy of "
+                              "the FP64 operator)", beta / bnorm);
+                why = msg;
                 result = DGTN_ENOCONV;
                 break;
             }
@@ -1299,7 +1383,9 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
                 // rounding at the attainable accuracy, or a stale direction: restart
                 // once per improvement of the true residual, else report stagnation
                 if (!(beta < breakdown_beta)) {
-                    why = "stagnated (p.Ap <= 0) at relative residual " + std::to_string(beta / bnorm);
+                    char msg[96];
+                    std::snprintf(msg, sizeof msg, "stagnated (p.Ap <= 0) at relative residual %.3e", beta / bnorm);
+                    why = msg;
                     result = DGTN_ENOCONV;
                     break;
                 }

@@ -239,3 +239,41 @@ def test_multigrid_with_overlapping_smoother(prec):
     tol = 1e-12 if prec == 64 else 1e-5
     assert abs(a - b) < tol * float(torch.linalg.norm(v) * torch.linalg.norm(Mw))
     assert float(torch.sum(v * Mv)) > 0
+
+
+def _multilayer_box():
+    layers = [{"thickness": 0.01, "n_elem": 1, "ratio": 1.0, "material": 1 + (i % 2)} for i in range(12)]
+    layers.append({"thickness": 0.88, "n_elem": 4, "ratio": 1.8, "material": 0})
+    return W.box(nx=4, ny=4, Lx=2.0, Ly=2.0, p=3, layers=layers,
+                 materials=[W.FUSED_SILICA, W.CRYSTAL_A, W.CRYSTAL_B])
+
+
+def test_fiducial_layer_coarsening():
+    # 16 columns x 16 z-elements: the N = 2 level still has 6144 unknowns, so the
+    # hierarchy merges z-element pairs (mixed crystal pairs become effective materials)
+    spec = _multilayer_box()
+    P = dgtn.Problem(spec)
+    o = dgtn.default_opts(64, rtol=1e-11, max_iter=4000)
+    levels = []
+    while True:
+        try:
+            levels.append(P.level_info(o, len(levels)))
+        except dgtn.DgtnError:
+            break
+    assert levels[-1][1] < levels[-2][1], levels       # the last level merged z-elements
+    P.bind(o)
+    u, st = P.solve(opts=o, raise_on_noconv=False)      # runs to the FP64 residual floor
+    o3 = dgtn.default_opts(64, rtol=1e-11, max_iter=4000, mg_levels=2)   # no merged layers
+    P.bind(o3)
+    u3, st3 = P.solve(opts=o3, raise_on_noconv=False)
+    assert st.rel_res < 1e-9 and st3.rel_res < 1e-9, (st.rel_res, st3.rel_res)
+    np.testing.assert_allclose(P.energy(u), P.energy(u3), rtol=1e-9)
+    o8 = dgtn.default_opts(64, rtol=1e-8, max_iter=4000)
+    P.bind(o8)
+    _, s8 = P.solve(opts=o8)
+    assert s8.iters < 60, s8.iters
+    v = _dev(W.random_field(spec, 5))
+    w = _dev(W.random_field(spec, 6))
+    Mv, Mw = P.precondition(v, o8), P.precondition(w, o8)
+    a, b = float(torch.sum(w * Mv)), float(torch.sum(v * Mw))
+    assert abs(a - b) < 1e-12 * float(torch.linalg.norm(v) * torch.linalg.norm(Mw))
