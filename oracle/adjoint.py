@@ -1,16 +1,20 @@
 """Oracle: gradient of the layer-weighted elastic energy J = sum_k w_k U_k.
 
-Sec. 2.1 defines U_k; with A u = b (Sec. 2.3) and a load that does not depend
-on the parameters, the adjoint identity gives
-    dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u,   A^T lambda = K_w u,
-K_w the layer-weighted energy form, A^T = A for the weak-form operator.  The
+Sec. 2.1 defines U_k; with A u = b (Sec. 2.3) the adjoint identity gives
+    dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u + lambda^T b_theta,
+    A^T lambda = K_w u,
+K_w the layer-weighted energy form, A^T = A for the weak-form operator.
+Materials and thicknesses change A and K_w (the load on z = 0 does not move);
+the beam width r0 and centre xc, yc of eq. laserbeam change only b.  The
 oracle solves both systems with its own solver (dense on tiny meshes) and
-evaluates the two contractions by five-point central differences of its own
-operator and energy in the parameter (exact up to rounding where they are
-linear, i.e. for the moduli; O(step^4) for Poisson ratios and thicknesses).
+evaluates the three contractions by five-point central differences of its own
+operator, energy and load in the parameter (exact up to rounding where they
+are linear, i.e. for the moduli; O(step^4) otherwise).
 
-Pinned by tests: Euler homogeneity sum_m c_m dU/dc_m = -U for all moduli,
-agreement with finite differences of the whole pipeline.
+Pinned by tests: Euler homogeneity sum_m c_m dU/dc_m = -U for all moduli;
+length scaling sum_l l dU/dl = -U over every length of a box (sides, layer
+thicknesses, beam width and centre); reflection symmetry of the beam-centre
+derivatives; agreement with finite differences of the whole pipeline.
 """
 from __future__ import annotations
 
@@ -21,7 +25,7 @@ import numpy as np
 from . import dg, solve
 from .geometry import ref_deriv_T
 
-PARAM_KINDS = ("c11", "c12", "c44", "youngs", "poisson", "thickness")
+PARAM_KINDS = ("c11", "c12", "c44", "youngs", "poisson", "thickness", "r0", "xc", "yc")
 
 
 def energy_grad_u(prob, u, w_layers=None):
@@ -41,6 +45,8 @@ def energy_grad_u(prob, u, w_layers=None):
 def get_param(spec, kind, index):
     if kind == "thickness":
         return spec["layers"][index]["thickness"]
+    if kind in ("r0", "xc", "yc"):
+        return spec["load"][kind]
     m = spec["materials"][index]
     if kind in ("c11", "c12", "c44"):
         if m["kind"] == "cubic":
@@ -57,6 +63,9 @@ def set_param(spec, kind, index, value):
     s = copy.deepcopy(spec)
     if kind == "thickness":
         s["layers"][index]["thickness"] = value
+        return s
+    if kind in ("r0", "xc", "yc"):
+        s["load"][kind] = value
         return s
     m = s["materials"][index]
     if kind in ("c11", "c12", "c44"):
@@ -87,11 +96,18 @@ def solve_state(spec, dense=True, w_layers=None):
 
 
 def functional(spec, u, lam, w_layers=None):
-    """1/2 u^T K_w u - lambda^T A u for fixed u, lambda under `spec`."""
+    """1/2 u^T K_w u - lambda^T A u + lambda^T b for fixed u, lambda under `spec`."""
     P = dg.Problem(spec)
     U = dg.energy_layers(P, u)
     w = np.ones(len(U)) if w_layers is None else np.asarray(w_layers, float)
-    return float(np.dot(w, U)) - float(np.sum(lam * dg.apply(P, u)))
+    return float(np.dot(w, U)) - float(np.sum(lam * dg.apply(P, u))) + float(np.sum(lam * dg.rhs(P)))
+
+
+def param_step(spec, kind, index, rel_step):
+    """Difference step: relative to the parameter, for the beam centre relative to r0."""
+    if kind in ("xc", "yc"):
+        return rel_step * spec["load"]["r0"]
+    return rel_step * abs(get_param(spec, kind, index))
 
 
 def gradient(spec, params, w_layers=None, rel_step=1e-3, dense=True):
@@ -103,7 +119,7 @@ def gradient(spec, params, w_layers=None, rel_step=1e-3, dense=True):
     out = []
     for kind, index in params:
         t0 = get_param(spec, kind, index)
-        h = rel_step * abs(t0)
+        h = param_step(spec, kind, index, rel_step)
         f = [functional(set_param(spec, kind, index, t0 + s * h), u, lam, w_layers) for s in (-2, -1, 1, 2)]
         out.append((f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h))
     return J, np.array(out)

@@ -4,6 +4,12 @@
   the elastic constants (the penalty uses averaged moduli), so u scales as 1/s
   and U as 1/s when every constant is multiplied by s:
   sum_m c_m dU/dc_m = -U, and per isotropic material Y dU/dY sums the same way.
+* Length scaling: the operator scales as s and the load vector is unchanged
+  when every length (box sides, layer thicknesses, beam width and centre) is
+  multiplied by s, so U scales as 1/s: sum_l l dU/dl = -U.  The box sides are
+  differenced through the whole pipeline, the other lengths come from the
+  oracle's gradient.
+* Reflection symmetry of the beam-centre derivatives on a square box.
 * Finite differences of the whole pipeline (re-mesh, re-assemble, solve,
   energy), which share nothing with the adjoint identity.
 * dJ/du: K_w u is the derivative of J at fixed parameters (checked against a
@@ -28,6 +34,13 @@ def pipeline_energy(spec, w):
     P = dg.Problem(spec)
     u = solve.pcg(P, dg.rhs(P), rtol=1e-14, maxit=5000)[0]
     return float(np.dot(w, dg.energy_layers(P, u)))
+
+
+def offset_spec(xc=0.12, yc=-0.07):
+    # the tiny box under a wider beam whose centre is off the axis
+    s = tiny_spec()
+    s["load"] = {"F0": 1.0, "r0": 0.25, "xc": xc, "yc": yc}
+    return s
 
 
 @pytest.fixture(scope="module")
@@ -59,13 +72,43 @@ def test_layer_weights_split(spec):
     np.testing.assert_allclose(g, 0.3 * g0 + 1.7 * g1, rtol=1e-9)
 
 
-@pytest.mark.parametrize("param", [("c11", 1), ("poisson", 0), ("thickness", 0)])
-def test_against_pipeline_differences(spec, param):
+def test_length_scaling():
+    spec = offset_spec()
+    w = np.array([0.3, 1.7])
+    lengths = [("thickness", 0), ("thickness", 1), ("r0", 0), ("xc", 0), ("yc", 0)]
+    J, g = adjoint.gradient(spec, lengths, w_layers=w)
+    total = sum(adjoint.get_param(spec, k, i) * gi for (k, i), gi in zip(lengths, g))
+    for side in ("Lx", "Ly"):
+        L0 = spec[side]
+        h = 1e-4 * L0
+        fp = pipeline_energy(W.with_overrides(spec, **{side: L0 + h}), w)
+        fm = pipeline_energy(W.with_overrides(spec, **{side: L0 - h}), w)
+        total += L0 * (fp - fm) / (2 * h)
+    assert abs(total + J) < 1e-7 * J
+    # every term matters: the beam terms alone are a sizeable part of the sum
+    assert abs(g[2] * 0.25) > 1e-2 * J and abs(g[3]) > 0 and abs(g[4]) > 0
+
+
+def test_beam_centre_reflection():
+    # x -> -x maps the beam at xc to the beam at -xc; x <-> y swaps xc and yc
+    params = [("xc", 0), ("yc", 0)]
+    _, ga = adjoint.gradient(offset_spec(0.12, -0.07), params)
+    _, gb = adjoint.gradient(offset_spec(-0.12, -0.07), params)
+    _, gc = adjoint.gradient(offset_spec(-0.07, 0.12), params)
+    _, g0 = adjoint.gradient(offset_spec(0.0, 0.0), params)
+    np.testing.assert_allclose(gb, [-ga[0], ga[1]], rtol=1e-9)
+    np.testing.assert_allclose(gc, [ga[1], ga[0]], rtol=1e-9)
+    assert np.max(np.abs(g0)) < 1e-9 * np.max(np.abs(ga))
+
+
+@pytest.mark.parametrize("param", [("c11", 1), ("poisson", 0), ("thickness", 0), ("r0", 0), ("xc", 0)])
+def test_against_pipeline_differences(param):
+    spec = offset_spec() if param[0] in ("r0", "xc") else tiny_spec()
     w = np.array([0.3, 1.7])
     _, g = adjoint.gradient(spec, [param], w_layers=w)
     kind, index = param
     t0 = adjoint.get_param(spec, kind, index)
-    h = 1e-4 * abs(t0)
+    h = adjoint.param_step(spec, kind, index, 1e-4)
     fp = pipeline_energy(adjoint.set_param(spec, kind, index, t0 + h), w)
     fm = pipeline_energy(adjoint.set_param(spec, kind, index, t0 - h), w)
     fd = (fp - fm) / (2 * h)
