@@ -424,7 +424,7 @@ def summarize_profiles(prof_dir, commands):
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
          "hbm_bytes_per_launch": fetch + write, "algorithmic_bytes_per_launch": apply_bytes(spec, 8),
          "fetch_calibration_factor": fetch_factor, "write_calibration_factor": write_factor,
-         "kernels_hip_sha256_16": kernel_source_hash(), "commands": commands}
+         "operator_source_sha256_16": kernel_source_hash(), "commands": commands}
     json.dump(d, open(os.path.join(out_dir, "k_apply_config2_traffic.json"), "w"), indent=1)
     txt = ["# HBM traffic of k_apply<7,double> on the thin-coating cylinder (2,058,000 DoF)", "",
            f"FETCH_SIZE per launch {np.mean(f):.0f} KiB x {fetch_factor:.3f} = {fetch / 1e6:.2f} MB",
@@ -438,9 +438,12 @@ def summarize_profiles(prof_dir, commands):
 
 
 def kernel_source_hash():
+    """Hash of the sources k_apply is compiled from (kernel, device helpers, level view)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2111_06893_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "element.h", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2111_06893_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -450,7 +453,7 @@ def measured_traffic():
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+    if d.get("operator_source_sha256_16") != kernel_source_hash():
         return None
     return d["hbm_bytes_per_launch"]
 

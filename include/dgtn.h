@@ -220,9 +220,13 @@ dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers,
  * c11 = lambda + 2 mu, c12 = lambda, c44 = mu); DGTN_PARAM_YOUNGS / POISSON:
  * Young's modulus / Poisson ratio of isotropic material `index`;
  * DGTN_PARAM_THICKNESS: thickness of layer `index` (all its element
- * thicknesses scale with it, the layers below translate). */
+ * thicknesses scale with it, the layers below translate);
+ * DGTN_PARAM_BEAM_WIDTH / BEAM_X / BEAM_Y: the width r0 and the centre xc, yc
+ * of the Gaussian pressure of eq. laserbeam, the beam shape and position a
+ * search over mirror configurations (Sec. 4) varies (`index` unused). */
 enum { DGTN_PARAM_C11 = 0, DGTN_PARAM_C12 = 1, DGTN_PARAM_C44 = 2, DGTN_PARAM_YOUNGS = 3,
-       DGTN_PARAM_POISSON = 4, DGTN_PARAM_THICKNESS = 5 };
+       DGTN_PARAM_POISSON = 4, DGTN_PARAM_THICKNESS = 5, DGTN_PARAM_BEAM_WIDTH = 6,
+       DGTN_PARAM_BEAM_X = 7, DGTN_PARAM_BEAM_Y = 8 };
 typedef struct {
     int kind;
     int index;
@@ -236,12 +240,14 @@ dgtn_status dgtn_energy_grad(dgtn_ctx* ctx, const double* u, const double* w_lay
                              hipStream_t stream);
 
 /* Adjoint gradient of J = sum_k w_k U_k with respect to n_params parameters:
- *   dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u,
+ *   dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u + lambda^T b_theta,
  * u the solution of A u = b and lambda that of A lambda = dJ/du (A is
- * symmetric; the load does not depend on the parameters).  A_theta u and
- * K_w,theta are evaluated exactly by the operator and energy kernels on dual
- * numbers.  u, lam: device double; dJ: host, n_params values.  Available for
- * p <= 6 (DGTN_EINVAL otherwise).  Synchronises the stream. */
+ * symmetric).  Material and thickness parameters leave b unchanged and beam
+ * parameters leave A and K unchanged.  A_theta u and K_w,theta are evaluated
+ * exactly by the operator and energy kernels on dual numbers, b_theta by the
+ * load kernel with the derivative of the pressure profile.  u, lam: device
+ * double; dJ: host, n_params values.  Available for p <= 6 (DGTN_EINVAL
+ * otherwise, and for an unknown kind or index).  Synchronises the stream. */
 dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const double* w_layers,
                       int n_params, const dgtn_param* params, double* dJ, hipStream_t stream);
 

@@ -16,10 +16,12 @@ from . import _lib
 from ._lib import DgtnError, check, load
 
 __all__ = ["Problem", "DgtnError", "noise_psd", "noise_psd_parts", "load", "problem_struct", "default_opts", "PARAM_KINDS",
-           "with_params", "EnergyFn", "layer_energies"]
+           "with_params", "param_value", "EnergyFn", "layer_energies"]
 
 # Parameter kinds of the energy gradient (dgtn_param.kind)
-PARAM_KINDS = {"c11": 0, "c12": 1, "c44": 2, "youngs": 3, "poisson": 4, "thickness": 5}
+PARAM_KINDS = {"c11": 0, "c12": 1, "c44": 2, "youngs": 3, "poisson": 4, "thickness": 5,
+               "r0": 6, "xc": 7, "yc": 8}
+_LOAD_KINDS = ("r0", "xc", "yc")  # beam width and centre of the pressure profile (index unused)
 
 _BC = {"top", "bottom", "side"}
 
@@ -69,6 +71,9 @@ def with_params(spec, params, values):
         if kind == "thickness":
             s["layers"][index]["thickness"] = v
             continue
+        if kind in _LOAD_KINDS:
+            s["load"][kind] = v
+            continue
         m = s["materials"][index]
         if kind in ("c11", "c12", "c44"):
             if m["kind"] != "cubic":
@@ -81,6 +86,22 @@ def with_params(spec, params, values):
         else:
             raise ValueError(f"unknown parameter kind {kind!r}")
     return s
+
+
+def param_value(spec, kind, index):
+    """Value of the parameter (kind, index) in spec (see with_params)."""
+    if kind == "thickness":
+        return float(spec["layers"][index]["thickness"])
+    if kind in _LOAD_KINDS:
+        return float(spec["load"][kind])
+    m = spec["materials"][index]
+    if kind in ("c11", "c12", "c44"):
+        return float(m[kind] if m["kind"] == "cubic" else _cubic_constants(m)[kind])
+    if kind in ("youngs", "poisson"):
+        if m["kind"] != "iso":
+            raise ValueError(f"material {index} is not isotropic")
+        return float(m["Y"] if kind == "youngs" else m["nu"])
+    raise ValueError(f"unknown parameter kind {kind!r}")
 
 
 def noise_psd_parts(U_parts, phi_parts, T, f, F0):

@@ -1,11 +1,16 @@
 // Adjoint gradient of the layer-weighted elastic energy J = sum_k w_k U_k.
 //
-// With A u = b and the load independent of the parameters,
-//   dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u,   A lambda = K_w u,
+// With A u = b,
+//   dJ/dtheta = 1/2 u^T K_w,theta u - lambda^T A_theta u + lambda^T b_theta,
+//   A lambda = K_w u,
 // K_w the layer-weighted energy form (A is symmetric, so the adjoint system is
-// the forward one).  A_theta u and K_w,theta are evaluated by the forward
+// the forward one).  Material and thickness parameters leave the load on
+// z = 0 unchanged: A_theta u and K_w,theta are evaluated by the forward
 // operator and energy kernels instantiated on dual numbers, with the
-// derivative of the seeded material constants or element thicknesses.
+// derivative of the seeded material constants or element thicknesses.  The
+// beam parameters (width r0, centre xc, yc of the pressure of eq. laserbeam)
+// leave A and K unchanged: only lambda^T b_theta remains, b_theta being the
+// load kernel with the derivative of the pressure profile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +40,25 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_deriv(const double* __restr
     const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
     double acc = 0;
     for (size_t q = lo + tid; q < hi; q += kDotThreads) acc += lam[q] * Au[q].d;
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) partial[blockIdx.x] = red[0];
+}
+
+// partial[blk] = sum over the block's slice of lam[q] * b[q] (fixed order)
+__global__ __launch_bounds__(kDotThreads) void k_dot_plain(const double* __restrict__ lam,
+                                                           const double* __restrict__ b, size_t n,
+                                                           double* __restrict__ partial, int nblk) {
+    __shared__ double red[kDotThreads];
+    const int tid = threadIdx.x;
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double acc = 0;
+    for (size_t q = lo + tid; q < hi; q += kDotThreads) acc += lam[q] * b[q];
     red[tid] = acc;
     __syncthreads();
     for (int s = kDotThreads / 2; s > 0; s >>= 1) {
@@ -192,7 +216,11 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
             set_error("no such layer");
             return DGTN_EINVAL;
         }
-        if (!mod && !iso && p.kind != DGTN_PARAM_THICKNESS) { set_error("unknown parameter kind"); return DGTN_EINVAL; }
+        const bool beam = p.kind == DGTN_PARAM_BEAM_WIDTH || p.kind == DGTN_PARAM_BEAM_X || p.kind == DGTN_PARAM_BEAM_Y;
+        if (!mod && !iso && !beam && p.kind != DGTN_PARAM_THICKNESS) {
+            set_error("unknown parameter kind");
+            return DGTN_EINVAL;
+        }
     }
     dgtn_status st = upload_weights(c, w_layers, s);
     if (st != DGTN_OK) return st;
@@ -210,6 +238,23 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
     std::vector<double> part(A.nblk);
     for (int ip = 0; ip < n_params; ++ip) {
         const dgtn_param& p = params[ip];
+        if (p.kind >= DGTN_PARAM_BEAM_WIDTH) {
+            // lambda^T b_theta, b_theta written over the dual scratch vector
+            const Problem& P = c->prob;
+            double* db = at<double>(c, A.Au);
+            AHIP(launch_rhs(view_of<double>(c, L), reinterpret_cast<const double*>(c->ws + L.off_xy), P.F0, P.r0,
+                            P.xc, P.yc, p.kind - DGTN_PARAM_BEAM_WIDTH + 1, db, s));
+            hipLaunchKernelGGL(k_dot_plain, dim3(A.nblk), dim3(kDotThreads), 0, s, lam, db, n,
+                               at<double>(c, A.partial), A.nblk);
+            AHIP(hipGetLastError());
+            AHIP(hipMemcpyAsync(part.data(), at<double>(c, A.partial), 8 * part.size(), hipMemcpyDeviceToHost, s));
+            AHIP(hipStreamSynchronize(s));
+            double lb = 0;
+            for (double x : part) lb += x;
+            dJ[ip] = lb;
+            if (!std::isfinite(dJ[ip])) { set_error("non-finite gradient"); return DGTN_ENAN; }
+            continue;
+        }
         for (int iz = 0; iz < L.n_z; ++iz) hz[iz] = Dual(L.hz[iz], 0.0);
         for (size_t q = 0; q < mat.size(); ++q) mat[q] = Dual(c->matc[q] / yr, 0.0);
         if (p.kind == DGTN_PARAM_THICKNESS) {

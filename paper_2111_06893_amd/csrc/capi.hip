@@ -312,7 +312,7 @@ dgtn_status dgtn_rhs(dgtn_ctx* c, double* b, hipStream_t s) {
     const Level& L = c->levels[0];
     auto v = view_of<double>(c, L);
     const auto& P = c->prob;
-    HIP_CHECK(launch_rhs(v, reinterpret_cast<const double*>(c->ws + L.off_xy), P.F0, P.r0, P.xc, P.yc, b, s));
+    HIP_CHECK(launch_rhs(v, reinterpret_cast<const double*>(c->ws + L.off_xy), P.F0, P.r0, P.xc, P.yc, 0, b, s));
     return DGTN_OK;
 }
 

@@ -61,7 +61,7 @@ hipError_t launch_traction(const LevelView<R>& L, const R* u, R* tau, hipStream_
 template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s);
 hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
-                      double* b, hipStream_t s);
+                      int mode, double* b, hipStream_t s);
 template <typename R>
 hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s);
 hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s);

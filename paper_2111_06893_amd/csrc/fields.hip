@@ -1,0 +1,258 @@
+// gfx950 kernels of the load vector and the elastic energy (Sec. 2.1 and eq.
+// laserbeam): one workgroup per element, one lane per LGL node, the element's
+// displacement staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "element.h"
+
+namespace dgtn {
+
+namespace {
+
+// Load vector of the Gaussian pressure on DGTN_BC_PRESSURE faces:
+// b = -w_face J^Sigma n p(r), which is +z on the loaded face z = 0.
+// mode 0: p itself; 1, 2, 3: its derivative with respect to the beam width r0
+// and the beam centre xc, yc (the load vector's parameter derivatives).
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_rhs(LevelView<double> L, const double* __restrict__ xy,
+                                                         double F0, double r0, double xc, double yc, int mode,
+                                                         double* __restrict__ b) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid >= N3) return;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
+    const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
+    double acc[3] = {0, 0, 0};
+    const bool fi = (i == 0) | (i == N - 1), fj = (j == 0) | (j == N - 1), fk = (k == 0) | (k == N - 1);
+    const int faces[3] = {fi ? (i == 0 ? 0 : 1) : -1, fj ? (j == 0 ? 2 : 3) : -1, fk ? (k == 0 ? 4 : 5) : -1};
+    const double x = xy[(size_t)col * 2 * N2 + j * N + i] - xc;
+    const double y = xy[(size_t)col * 2 * N2 + N2 + j * N + i] - yc;
+    const double rho2 = x * x + y * y, ir2 = 1.0 / (r0 * r0);
+    double p = F0 * exp(-rho2 * ir2) / (M_PI * r0 * r0);
+    if (mode == 1) p *= 2.0 * (rho2 * ir2 - 1.0) / r0;
+    else if (mode == 2) p *= 2.0 * x * ir2;
+    else if (mode == 3) p *= 2.0 * y * ir2;
+    for (int q = 0; q < 3; ++q) {
+        const int f = faces[q];
+        if (f < 0) continue;
+        const Nbr nb = neighbour(L, col, iz, f);
+        if (nb.bc != DGTN_BC_PRESSURE) continue;
+        double n[3], amag, wsig;
+        face_normal(f, g, n, amag);
+        if (f >= 4) wsig = L.w[i] * L.w[j] * g.det2;
+        else if (f < 2) wsig = L.w[j] * L.w[k] * 0.5 * g.hz * g.det2 * amag;
+        else wsig = L.w[i] * L.w[k] * 0.5 * g.hz * g.det2 * amag;
+        for (int c = 0; c < 3; ++c) acc[c] -= wsig * n[c] * p;
+    }
+    double* be = b + (size_t)e * 3 * N3;
+    for (int c = 0; c < 3; ++c) be[c * N3 + tid] = acc[c];
+}
+
+// Per-element energy 1/2 sum_nodes w J D_(i u_j) Y D_(k u_l), in units of y_ref.
+// Arithmetic type R (double, or Dual for its derivative along a parameter).
+template <int N, typename R>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<R> L, const double* __restrict__ u,
+                                                            R* __restrict__ Ue) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = threads_for<N>();
+    __shared__ R su[3 * N3];
+    __shared__ R sD[N2];
+    __shared__ R red[NT];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = R(ue[q]);
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    __syncthreads();
+    R dens = 0;
+    if (tid < N3) {
+        const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+        const int col = e % L.n_cols, iz = e / L.n_cols;
+        const NodeGeo<R> g = node_geo<N>(L, col, iz, i, j);
+        R G[3][3], S[6], T[6];
+        gradient<N>(su, sD, i, j, k, g, G);
+        sym_of(G, S);
+        const int m = L.zmat[iz];
+        cubic_stress(L.mat[3 * m], L.mat[3 * m + 1], L.mat[3 * m + 2], S, T);
+        const R sdt = S[0] * T[0] + S[1] * T[1] + S[2] * T[2] + R(2) * (S[3] * T[3] + S[4] * T[4] + S[5] * T[5]);
+        dens = R(0.25) * L.w[i] * L.w[j] * L.w[k] * g.det2 * g.hz * sdt;
+    }
+    red[tid] = dens;
+    __syncthreads();
+    // fixed-order reduction (deterministic): strided sums into 64 slots, then a tree
+    if (tid < 64) {
+        R acc = 0;
+        for (int q = tid; q < NT; q += 64) acc += red[q];
+        red[tid] = acc;
+    }
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) Ue[e] = red[0];
+}
+
+// Per element, the three quadrature sums from which every per-modulus part of the
+// energy follows (the moduli are applied on the host):
+//   A = 1/2 int sum_i S_ii^2,   B = int sum_{i<j} S_ii S_jj,   C = 2 int sum_{i<j} S_ij^2,
+// so that U = c11 A + c12 B + c44 C and the bulk part is K (A + B).
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy_invariants(LevelView<double> L,
+                                                                      const double* __restrict__ u,
+                                                                      double* __restrict__ abc) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = threads_for<N>();
+    __shared__ double su[3 * N3];
+    __shared__ double sD[N2];
+    __shared__ double red[3][NT];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    __syncthreads();
+    double a = 0, b = 0, c = 0;
+    if (tid < N3) {
+        const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+        const int col = e % L.n_cols, iz = e / L.n_cols;
+        const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
+        double G[3][3], S[6];
+        gradient<N>(su, sD, i, j, k, g, G);
+        sym_of(G, S);
+        const double wJ = L.w[i] * L.w[j] * L.w[k] * g.det2 * 0.5 * g.hz;
+        a = wJ * 0.5 * (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+        b = wJ * (S[0] * S[1] + S[1] * S[2] + S[0] * S[2]);
+        c = wJ * 2.0 * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
+    }
+    red[0][tid] = a;
+    red[1][tid] = b;
+    red[2][tid] = c;
+    __syncthreads();
+    if (tid < 64) {  // fixed-order reduction
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int q = tid; q < NT; q += 64) {
+            s0 += red[0][q];
+            s1 += red[1][q];
+            s2 += red[2][q];
+        }
+        red[0][tid] = s0;
+        red[1][tid] = s1;
+        red[2][tid] = s2;
+    }
+    __syncthreads();
+    for (int st = 32; st > 0; st >>= 1) {
+        if (tid < st) {
+            red[0][tid] += red[0][tid + st];
+            red[1][tid] += red[1][tid + st];
+            red[2][tid] += red[2][tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid < 3) abc[(size_t)e * 3 + tid] = red[tid][0];
+}
+
+// g = scale * w(layer) * sum_m Dhat_m^T [w J (J^-1)^m_i Y^{ijkl} D_(k u_l)]: the
+// derivative with respect to u of the layer-weighted energy sum_k w_k U_k.
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_energy_grad(LevelView<double> L, const double* __restrict__ u,
+                                                                 const double* __restrict__ wz,
+                                                                 double* __restrict__ gout, double scale) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    __shared__ double sbuf[9 * N3];
+    __shared__ double sD[N2];
+    double* su = sbuf;
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* ue = u + (size_t)e * 3 * N3;
+    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
+    for (int q = tid; q < N2; q += blockDim.x) sD[q] = L.D[q];
+    __syncthreads();
+    const bool act = tid < N3;
+    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
+    double Fr[9];
+    if (act) {
+        const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
+        double G[3][3], S[6], T[6];
+        gradient<N>(su, sD, i, j, k, g, G);
+        sym_of(G, S);
+        const int m = L.zmat[iz];
+        cubic_stress(L.mat[3 * m], L.mat[3 * m + 1], L.mat[3 * m + 2], S, T);
+        const double wJ = L.w[i] * L.w[j] * L.w[k] * g.det2 * 0.5 * g.hz;
+        const double dz = 2.0 / g.hz;
+        const double Tx[3] = {T[0], T[3], T[4]}, Ty[3] = {T[3], T[1], T[5]}, Tz[3] = {T[4], T[5], T[2]};
+        for (int c = 0; c < 3; ++c) {
+            Fr[c] = wJ * (g.axx * Tx[c] + g.axy * Ty[c]);
+            Fr[3 + c] = wJ * (g.aex * Tx[c] + g.aey * Ty[c]);
+            Fr[6 + c] = wJ * dz * Tz[c];
+        }
+    }
+    __syncthreads();
+    if (act)
+        for (int s = 0; s < 9; ++s) sbuf[s * N3 + tid] = Fr[s];
+    __syncthreads();
+    if (!act) return;
+    const double wl = wz[iz] * scale;
+    for (int c = 0; c < 3; ++c) {
+        double r = 0;
+        for (int a = 0; a < N; ++a) {
+            r += sD[a * N + i] * sbuf[(0 + c) * N3 + k * N2 + j * N + a];
+            r += sD[a * N + j] * sbuf[(3 + c) * N3 + k * N2 + a * N + i];
+            r += sD[a * N + k] * sbuf[(6 + c) * N3 + a * N2 + j * N + i];
+        }
+        gout[(size_t)e * 3 * N3 + c * N3 + tid] = wl * r;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
+                      int mode, double* b, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_rhs<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, xy, F0, r0, xc, yc, mode, b);
+        return hipGetLastError();
+    });
+}
+
+template <typename R>
+hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy<NN, R>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy_invariants<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, abc);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_energy_grad(const LevelView<double>& L, const double* u, const double* wz, double* g, double scale,
+                              hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy_grad<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, wz, g, scale);
+        return hipGetLastError();
+    });
+}
+
+template <>
+hipError_t launch_energy<Dual>(const LevelView<Dual>& L, const double* u, Dual* Ue, hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_energy<NN, Dual>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, u, Ue);
+        return hipGetLastError();
+    });
+}
+
+template hipError_t launch_energy<double>(const LevelView<double>&, const double*, double*, hipStream_t);
+
+}  // namespace dgtn

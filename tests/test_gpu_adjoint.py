@@ -8,6 +8,11 @@
   five-point differences of the library's own solve-and-energy pipeline to
   1e-6 (coating 0.05 thick), and obeys Euler's relation
   Y_coat dU/dY_coat + Y_sub dU/dY_sub = -U (coating 1e-3 thick, to 1e-7).
+* The beam width and centre (the load's parameters): the library's
+  lambda^T b_theta equals the oracle's gradient on the box under an off-axis
+  beam (1e-8), the oracle's five-point difference of the functional given the
+  same u and lambda (1e-9), and differences of the library's pipeline on the
+  cylinder (1e-6).
 * The autograd function returns the oracle's weighted gradient.
 """
 import numpy as np
@@ -132,6 +137,51 @@ def test_energy_fn_backward(oracle_tiny):
     (U * torch.from_numpy(W_LAYERS)).sum().backward()
     _, ref = adjoint.gradient(spec, params, w_layers=W_LAYERS)
     np.testing.assert_allclose(theta.grad.numpy(), ref, rtol=1e-8)
+
+
+BEAM_PARAMS = [("r0", 0), ("xc", 0), ("yc", 0)]
+
+
+def offset_spec():
+    s = tiny_spec()
+    s["load"] = {"F0": 1.0, "r0": 0.25, "xc": 0.12, "yc": -0.07}
+    return s
+
+
+def test_beam_gradient_matches_oracle():
+    spec = offset_spec()
+    J, ref = adjoint.gradient(spec, BEAM_PARAMS, w_layers=W_LAYERS)
+    P, u, _, g = gpu_gradient(spec, BEAM_PARAMS, W_LAYERS)
+    assert abs(float(np.dot(W_LAYERS, P.energy(u))) - J) < 1e-10 * J
+    for (kind, _), a, b in zip(BEAM_PARAMS, g, ref):
+        assert abs(a - b) < 1e-8 * abs(b), (kind, a, b)
+
+
+def test_beam_gradient_with_given_state_is_exact():
+    spec = offset_spec()
+    _, u, lam = adjoint.solve_state(spec, w_layers=W_LAYERS)
+    P = dgtn.Problem(spec)
+    g = P.grad(torch.from_numpy(u).to("cuda"), torch.from_numpy(lam).to("cuda"), BEAM_PARAMS, W_LAYERS)
+    for (kind, index), a in zip(BEAM_PARAMS, g):
+        t0 = adjoint.get_param(spec, kind, index)
+        h = adjoint.param_step(spec, kind, index, 1e-3)
+        f = [adjoint.functional(adjoint.set_param(spec, kind, index, t0 + s * h), u, lam, W_LAYERS)
+             for s in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        assert abs(a - fd) < 1e-9 * abs(fd), (kind, a, fd)
+
+
+def test_beam_gradient_on_cylinder_against_differences():
+    spec = W.config1()
+    spec["load"] = {"F0": 1.0, "r0": 0.2, "xc": 0.3, "yc": 0.1}
+    params = [("r0", 0), ("xc", 0)]
+    _, _, _, g = gpu_gradient(spec, params, None, rtol=1e-11)
+    for (kind, index), a in zip(params, g):
+        t0 = adjoint.get_param(spec, kind, index)
+        h = 1e-3 * spec["load"]["r0"]
+        f = [gpu_total_energy(dgtn.with_params(spec, [(kind, index)], [t0 + s * h])) for s in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        assert abs(a - fd) < 1e-6 * abs(fd), (kind, a, fd)
 
 
 def test_grad_rejects_bad_parameters():
