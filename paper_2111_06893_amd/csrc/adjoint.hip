@@ -91,6 +91,7 @@ LevelView<Dual> dual_view(const dgtn_ctx* c) {
     v.E = L.E;
     v.geo2 = at<const Dual>(c, A.geo2);
     v.sig_side = at<const Dual>(c, A.sig);
+    v.fnrm = at<const Dual>(c, A.fnrm);
     v.cnbr = at<const int>(c, L.off_cnbr);
     v.cnf = at<const int>(c, L.off_cnf);
     v.hz = at<const Dual>(c, A.hz);
@@ -132,6 +133,7 @@ void plan_adjoint(dgtn_ctx* c, Layout& lay) {
     A.tau = lay.take(ds * (size_t)L.E * 6 * 3 * N2);
     A.geo2 = lay.take(ds * (size_t)L.n_cols * 5 * N2);
     A.sig = lay.take(ds * (size_t)L.n_cols * 4 * N);
+    A.fnrm = lay.take(ds * (size_t)L.n_cols * 4 * 3 * N);
     A.hz = lay.take(ds * (size_t)L.n_z);
     A.mat = lay.take(ds * c->matc.size());
     A.D = lay.take(ds * N2);
@@ -151,10 +153,11 @@ dgtn_status bind_adjoint(dgtn_ctx* c, hipStream_t s) {
     };
     std::vector<double> matn(c->matc.size());
     for (size_t i = 0; i < matn.size(); ++i) matn[i] = c->matc[i] / c->y_ref;
-    const auto g = to_dual(L.geo2), sg = to_dual(L.sig_side), hz = to_dual(L.hz), mt = to_dual(matn),
+    const auto g = to_dual(L.geo2), sg = to_dual(L.sig_side), fn = to_dual(L.fnrm), hz = to_dual(L.hz), mt = to_dual(matn),
                D = to_dual(L.lgl.D), w = to_dual(L.lgl.w);
     AHIP(up(A.geo2, g));
     AHIP(up(A.sig, sg));
+    AHIP(up(A.fnrm, fn));
     AHIP(up(A.hz, hz));
     AHIP(up(A.mat, mt));
     AHIP(up(A.D, D));

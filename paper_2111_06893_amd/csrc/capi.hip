@@ -34,6 +34,7 @@ LevelView<R> view_of(const dgtn_ctx* c, const Level& L) {
     char* b = c->ws;
     v.geo2 = reinterpret_cast<const R*>(b + L.off_geo2[pi]);
     v.sig_side = reinterpret_cast<const R*>(b + L.off_sig[pi]);
+    v.fnrm = reinterpret_cast<const R*>(b + L.off_fnrm[pi]);
     v.cnbr = reinterpret_cast<const int*>(b + L.off_cnbr);
     v.cnf = reinterpret_cast<const int*>(b + L.off_cnf);
     v.hz = reinterpret_cast<const R*>(b + L.off_hz[pi]);
@@ -71,6 +72,7 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
             const size_t rs = pi == 0 ? 8 : 4;
             L.off_geo2[pi] = lay.take(rs * L.n_cols * 5 * N2);
             L.off_sig[pi] = lay.take(rs * L.n_cols * 4 * N);
+            L.off_fnrm[pi] = lay.take(rs * L.n_cols * 4 * 3 * N);
             L.off_hz[pi] = lay.take(rs * L.n_z);
             L.off_mat[pi] = lay.take(rs * level_mat(c, L).size());
             L.off_D[pi] = lay.take(rs * N2);
@@ -253,6 +255,8 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
             HIP_CHECK(put32(L.off_geo2[1], L.geo2));
             HIP_CHECK(put64(L.off_sig[0], L.sig_side));
             HIP_CHECK(put32(L.off_sig[1], L.sig_side));
+            HIP_CHECK(put64(L.off_fnrm[0], L.fnrm));
+            HIP_CHECK(put32(L.off_fnrm[1], L.fnrm));
             HIP_CHECK(put64(L.off_hz[0], L.hz));
             HIP_CHECK(put32(L.off_hz[1], L.hz));
             std::vector<double> matn(level_mat(c, L));

@@ -13,7 +13,7 @@ namespace dgtn {
 // Workspace offsets of the adjoint's dual-number copies of the finest level.
 struct AdjointLayout {
     bool ok = false;  // allocated (the dual kernels cover N <= 7)
-    size_t wz = 0, u = 0, Au = 0, tau = 0, geo2 = 0, sig = 0, hz = 0, mat = 0, D = 0, w = 0, Ue = 0;
+    size_t wz = 0, u = 0, Au = 0, tau = 0, geo2 = 0, sig = 0, fnrm = 0, hz = 0, mat = 0, D = 0, w = 0, Ue = 0;
     size_t partial = 0, dots = 0;
     int nblk = 0;
 };

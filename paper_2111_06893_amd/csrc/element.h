@@ -106,6 +106,24 @@ __device__ __forceinline__ void face_normal(int f, const NodeGeo<R>& g, R n[3], 
     }
 }
 
+// The same from the per-column table of side-face normals (no square root or
+// division in the kernel); (i, j) is the node's position in the column.
+template <int N, typename R>
+__device__ __forceinline__ void face_frame(const LevelView<R>& L, int col, int f, int i, int j, R n[3], R& amag) {
+    if (f < 4) {
+        const R* t = L.fnrm + ((size_t)col * 4 + f) * 3 * N + (f < 2 ? j : i);
+        n[0] = t[0];
+        n[1] = t[N];
+        n[2] = 0;
+        amag = t[2 * N];
+    } else {
+        amag = 0;
+        n[0] = 0;
+        n[1] = 0;
+        n[2] = (f == 5) ? R(1) : R(-1);
+    }
+}
+
 // Flattened index of node (i, j, k) within face f (the face-buffer order).
 template <int N>
 __device__ __forceinline__ int face_index(int f, int i, int j, int k) {
@@ -189,6 +207,7 @@ struct FaceInfo {
     int e, f, flip, bc;   // neighbour element, its face, orientation; bc != 0 on boundaries
     R c11, c12, c44;      // averaged moduli on the face (own on boundaries)
     R hz;                 // neighbour thickness (own on boundaries)
+    R sig;                // z faces: penalty sigma, C N^2 / min(h, h_neighbour) (own h on boundaries)
 };
 
 template <int N, typename R>
@@ -207,6 +226,7 @@ __device__ __forceinline__ void load_faces(const LevelView<R>& L, int col, int i
         fi.c12 = R(0.5) * (L.mat[3 * m + 1] + L.mat[3 * mn + 1]);
         fi.c44 = R(0.5) * (L.mat[3 * m + 2] + L.mat[3 * mn + 2]);
         fi.hz = nb.bc == 0 ? L.hz[nb.e / L.n_cols] : L.hz[iz];
+        fi.sig = L.penalty_n2 / min(fi.hz, L.hz[iz]);
         sf[tid] = fi;
     } else if (tid == 6) {
         const int m = L.zmat[iz];
@@ -214,6 +234,7 @@ __device__ __forceinline__ void load_faces(const LevelView<R>& L, int col, int i
         sown[1] = L.mat[3 * m + 1];
         sown[2] = L.mat[3 * m + 2];
         sown[3] = L.hz[iz];
+        sown[4] = R(2) / L.hz[iz];
     }
 }
 
@@ -260,9 +281,9 @@ __device__ __forceinline__ void line_contract(const LevelView<R>& L, const R* sr
     R v[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) v[a] = src[base + a * stride];
-    // one row of D (or D^T) per output, loaded as the loop reaches it: the
-    // whole matrix would not fit the scalar register file
-#pragma unroll 1
+    // unrolled: the scalar loads of the rows of D are issued ahead of their use
+    // instead of one exposed load latency per output
+#pragma unroll
     for (int x = 0; x < N; ++x) {
         const R* row = (transpose ? L.Dt : L.Dk) + x * N;
         R acc = 0;
@@ -287,9 +308,8 @@ __device__ __forceinline__ void ref_derivatives(const LevelView<R>& L, const R* 
 
 // Physical gradient G[d][l] = D_d u_l at node q from the reference derivatives.
 template <int N, typename R>
-__device__ __forceinline__ void node_gradient(const R* sG, int q, const NodeGeo<R>& g, R G[3][3]) {
+__device__ __forceinline__ void node_gradient(const R* sG, int q, const NodeGeo<R>& g, R dz, R G[3][3]) {
     constexpr int N3 = N * N * N;
-    const R dz = R(2) / g.hz;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const R dxi = sG[l * N3 + q], deta = sG[(3 + l) * N3 + q], dzeta = sG[(6 + l) * N3 + q];

@@ -298,6 +298,22 @@ Level build_level(const Problem& P, int p, int refine, int p0, int r0) {
         const int m = (f < 2) ? 0 : 2;
         return 2.0 / std::hypot(g[m * N2 + q], g[(m + 1) * N2 + q]);
     };
+    // outward unit normals of the side faces and |grad xi^m| there (z-independent)
+    L.fnrm.assign((size_t)L.n_cols * 4 * 3 * N, 0.0);
+    for (int c = 0; c < L.n_cols; ++c)
+        for (int f = 0; f < 4; ++f)
+            for (int t = 0; t < N; ++t) {
+                int i, j;
+                side_node(f, t, N, i, j);
+                const double* g = &L.geo2[(size_t)c * 5 * N2];
+                const int q = j * N + i, m = (f < 2) ? 0 : 2;
+                const double ax = g[m * N2 + q], ay = g[(m + 1) * N2 + q], a = std::hypot(ax, ay);
+                const double s = (f & 1) ? 1.0 : -1.0;
+                double* o = &L.fnrm[((size_t)c * 4 + f) * 3 * N];
+                o[t] = s * ax / a;
+                o[N + t] = s * ay / a;
+                o[2 * N + t] = a;
+            }
     L.sig_side.assign((size_t)L.n_cols * 4 * N, 0.0);
     const double cn2 = L.pen_z * double(1 << (r0 - refine));
     for (int c = 0; c < L.n_cols; ++c)

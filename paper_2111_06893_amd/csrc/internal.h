@@ -29,6 +29,7 @@ struct LevelView {
     int N, n_cols, n_z, E;
     const R* geo2;       // [n_cols][5][N*N]: a^xi_x, a^xi_y, a^eta_x, a^eta_y, det2
     const R* sig_side;   // [n_cols][4][N]   penalty sigma on the side faces
+    const R* fnrm;       // [n_cols][4][3][N] side faces: outward unit normal n_x, n_y and |grad xi^m|
     const int* cnbr;     // [n_cols][4]      neighbour column or -1
     const int* cnf;      // [n_cols][4]      neighbour face | flip << 2, or the bc code if boundary
     const R* hz;         // [n_z]            element thickness
@@ -50,6 +51,7 @@ struct Level {
     double pen_z = 0;    // C (p0 + 1)^2 of the finest level, used on every level
     Lgl lgl;
     std::vector<double> geo2, xy, sig_side;
+    std::vector<double> fnrm;  // [n_cols][4][3][N]: n_x, n_y, |grad xi^m| at the side-face nodes
     std::vector<int> cnbr, cnf;
     std::vector<double> hz, ztop;
     std::vector<int> zmat, zlayer;
@@ -57,7 +59,7 @@ struct Level {
     // that use the problem's own materials (z-coarsened levels add effective ones)
     std::vector<double> mat;
     // workspace offsets (bytes) of the uploaded arrays, FP64 and FP32 mirrors
-    size_t off_geo2[2], off_sig[2], off_hz[2], off_mat[2], off_D[2], off_w[2];
+    size_t off_geo2[2], off_sig[2], off_fnrm[2], off_hz[2], off_mat[2], off_D[2], off_w[2];
     size_t off_cnbr, off_cnf, off_zmat, off_xy;
     size_t off_tau[2];   // face traction buffer [E][6][3][N*N]
 };

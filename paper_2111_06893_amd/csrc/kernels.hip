@@ -26,7 +26,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ R su[3 * N3];
     __shared__ R sG[9 * N3];
-    __shared__ R sown[4];
+    __shared__ R sown[5];
     const int e = xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
         sown[1] = L.mat[3 * m + 1];
         sown[2] = L.mat[3 * m + 2];
         sown[3] = L.hz[iz];
+        sown[4] = R(2) / L.hz[iz];
     }
     const bool act = tid < 6 * N2;
     const int f = tid / N2, fi = tid % N2;
@@ -48,12 +49,11 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     ref_derivatives<N>(L, su, sG, tid);
     __syncthreads();
     if (!act) return;
-    g.hz = sown[3];
     R G[3][3], S[6], T[6], n[3], amag, t[3];
-    node_gradient<N>(sG, k * N2 + j * N + i, g, G);
+    node_gradient<N>(sG, k * N2 + j * N + i, g, sown[4], G);
     sym_of(G, S);
     cubic_stress(sown[0], sown[1], sown[2], S, T);
-    face_normal(f, g, n, amag);
+    face_frame<N>(L, col, f, i, j, n, amag);
     traction(n, T, t);
     R* dst = tau + ((size_t)e * 6 + f) * 3 * N2 + fi;
     dst[0] = t[0];
@@ -73,26 +73,29 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
     __shared__ R sLF[6 * 3 * N2];     // per face node: lifting factor times the jump
     __shared__ R sw[N];
+    __shared__ R swi[N];
     __shared__ FaceInfo<R> sface[6];
-    __shared__ R sown[4];
+    __shared__ R sown[5];
     const int e = xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
     for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    for (int q = tid; q < N; q += blockDim.x) sw[q] = L.w[q];
+    for (int q = tid; q < N; q += blockDim.x) {
+        sw[q] = L.w[q];
+        swi[q] = R(1) / L.w[q];
+    }
     load_faces<N>(L, col, iz, tid, sface, sown);
     // node role
     const bool nact = tid < N3;
     const int i = tid % N, j = (tid / N) % N, k = tid / N2;
-    NodeGeo<R> g = nact ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
+    const NodeGeo<R> g = nact ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
     // face role
     const bool fact = tid < 6 * N2;
     const int f = tid / N2, fi = tid % N2;
     int fi_i = 0, fi_j = 0, fi_k = 0;
     if (fact) face_node<N>(f, fi, fi_i, fi_j, fi_k);
     __syncthreads();
-    g.hz = sown[3];
     // neighbour trace and traction of this face node: in flight during the derivatives
     R un[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     if (fact && sface[f].bc == 0) {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     const bool fxi = (i == 0) | (i == N - 1), feta = (j == 0) | (j == N - 1), fzeta = (k == 0) | (k == N - 1);
     if (nact) {
         R G[3][3], T[6], S[6];
-        node_gradient<N>(sG, tid, g, G);
+        node_gradient<N>(sG, tid, g, sown[4], G);
         sym_of(G, S);
 #pragma unroll
         for (int q = 0; q < 6; ++q) sG[q * N3 + tid] = S[q];
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
             for (int q = 0; q < 3; ++q) {
                 if (faces[q] < 0) continue;
                 R n[3], amag, t[3];
-                face_normal(faces[q], g, n, amag);
+                face_frame<N>(L, col, faces[q], i, j, n, amag);
                 traction(n, T, t);
                 const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
                 sFT[slot] = t[0];
@@ -142,29 +145,28 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     // 3. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
     if (fact) {
         // face geometry loaded here rather than held through the earlier phases (register pressure)
-        NodeGeo<R> gf = node_geo<N>(L, col, iz, fi_i, fi_j);
-        gf.hz = sown[3];
-        const R sig_side = f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : R(0);
+        const R det2 = L.geo2[(size_t)col * 5 * N2 + 4 * N2 + fi_j * N + fi_i];
+        const R hz = sown[3];
         const FaceInfo<R> fo = sface[f];
+        const R sigma = f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : fo.sig;
         R n[3], amag;
-        face_normal(f, gf, n, amag);
+        face_frame<N>(L, col, f, fi_i, fi_j, n, amag);
         R wsig, lr;
         if (f >= 4) {
-            wsig = sw[fi_i] * sw[fi_j] * gf.det2;
-            lr = R(2) / (sw[fi_k] * gf.hz);
+            wsig = sw[fi_i] * sw[fi_j] * det2;
+            lr = swi[fi_k] * sown[4];
         } else if (f < 2) {
-            wsig = sw[fi_j] * sw[fi_k] * R(0.5) * gf.hz * gf.det2 * amag;
-            lr = amag / sw[fi_i];
+            wsig = sw[fi_j] * sw[fi_k] * R(0.5) * hz * det2 * amag;
+            lr = amag * swi[fi_i];
         } else {
-            wsig = sw[fi_i] * sw[fi_k] * R(0.5) * gf.hz * gf.det2 * amag;
-            lr = amag / sw[fi_j];
+            wsig = sw[fi_i] * sw[fi_k] * R(0.5) * hz * det2 * amag;
+            lr = amag * swi[fi_j];
         }
         const int qn = fi_k * N2 + fi_j * N + fi_i;
         const int slot = f * 3 * N2 + fi;
         R jump[3] = {0, 0, 0}, flux[3] = {0, 0, 0};
         if (fo.bc == 0 || fo.bc == DGTN_BC_DIRICHLET) {
             const bool interior = fo.bc == 0;
-            const R sigma = (f < 4) ? sig_side : L.penalty_n2 / (interior ? min(gf.hz, fo.hz) : gf.hz);
 #pragma unroll
             for (int c = 0; c < 3; ++c) jump[c] = interior ? su[c * N3 + qn] - un[c] : R(2) * su[c * N3 + qn];
             R Sj[6], Tj[6], pen[3];
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
             if (faces[q] < 0) continue;
             const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
             R n[3], amag, lj[3], Sl[6];
-            face_normal(faces[q], g, n, amag);
+            face_frame<N>(L, col, faces[q], i, j, n, amag);
 #pragma unroll
             for (int c = 0; c < 3; ++c) lj[c] = sLF[slot + c * N2];
             sym_outer(n, lj, Sl);
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
         }
         R T[6];
         cubic_stress(c11, c12, c44, S, T);
-        const R wJ = sw[i] * sw[j] * sw[k] * g.det2 * R(0.5) * g.hz;
-        const R dz = R(2) / g.hz;
+        const R wJ = sw[i] * sw[j] * sw[k] * g.det2 * R(0.5) * sown[3];
+        const R dz = sown[4];
         const R Tx[3] = {T[0], T[3], T[4]};
         const R Ty[3] = {T[3], T[1], T[5]};
         const R Tz[3] = {T[4], T[5], T[2]};
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
         R v[N];
 #pragma unroll
         for (int a = 0; a < N; ++a) v[a] = line[a * stride];
-#pragma unroll 1
+#pragma unroll
         for (int x = 0; x < N; ++x) {
             const R* row = L.Dt + x * N;
             R acc = 0;
