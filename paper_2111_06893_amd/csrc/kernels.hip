@@ -61,17 +61,22 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     dst[2 * N2] = t[2];
 }
 
-// Six waves per SIMD: with the LDS below that fits three workgroups per CU (FP64,
-// N = 7) at the cost of a few spilled registers; measured faster than two.
+// Seven waves per SIMD: with the FP64 lift factors stored over u (below) the
+// LDS of four workgroups fits a CU at N = 7 (40.5 KB each), at the cost of a few
+// spilled registers; measured faster than three workgroups.
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, const R* __restrict__ u,
+__global__ __launch_bounds__(line_threads<N>(), 7) void k_apply(LevelView<R> L, const R* __restrict__ u,
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
     __shared__ R su[3 * N3];          // u
     __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F, then D^T F
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
-    __shared__ R sLF[6 * 3 * N2];     // per face node: lifting factor times the jump
+    // per face node: lifting factor times the jump.  In FP64 (N >= 6) it is written
+    // over u, which is dead once the face lanes have taken their jumps.
+    constexpr bool kLiftOverU = sizeof(R) == 8 && 6 * N2 <= N3;
+    __shared__ R sLFown[kLiftOverU ? 1 : 6 * 3 * N2];
+    R* const sLF = kLiftOverU ? su : sLFown;
     __shared__ R sw[N];
     __shared__ R swi[N];
     __shared__ FaceInfo<R> sface[6];
@@ -143,6 +148,7 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
     }
     __syncthreads();
     // 3. face lanes: jump, lift and numerical flux (eqs. numflux, penalty, bc)
+    R lfj[3] = {0, 0, 0};
     if (fact) {
         // face geometry loaded here rather than held through the earlier phases (register pressure)
         const R det2 = L.geo2[(size_t)col * 5 * N2 + 4 * N2 + fi_j * N + fi_i];
@@ -182,9 +188,14 @@ __global__ __launch_bounds__(line_threads<N>(), 6) void k_apply(LevelView<R> L, 
         // Neumann faces: no jump and, for homogeneous data, no flux
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sLF[slot + c * N2] = R(-0.5) * lr * jump[c];
+            lfj[c] = R(-0.5) * lr * jump[c];
             sFT[slot + c * N2] = -wsig * flux[c];
         }
+    }
+    if constexpr (kLiftOverU) __syncthreads();  // every face lane has read u
+    if (fact) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sLF[f * 3 * N2 + fi + c * N2] = lfj[c];
     }
     __syncthreads();
     // 4. node lanes: lifted strain, stress and the volume fluxes F^m_c = w J (J^-1)^m_d T^{dc}
