@@ -14,7 +14,9 @@ coating thickness), i.e. one more solve and the parameter derivatives.  The head
 applications / s) of the apply blocks inside the timed steps; the JSON line
 also carries the step breakdown, the FP32 apply rate, time-to-U of the FP64-
 and FP32-preconditioned solves, the roofline of the dominant kernel and the
-oracle's CPU rate on a bounded sample.
+oracle's CPU rate on a bounded sample.  An untimed record on the forty-layer
+crystalline coating (8000 elements, p = 5) gives the setup, solve and the
+gradient of the coating energy with respect to all forty coating thicknesses.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -184,6 +186,7 @@ def main():
     ap.add_argument("--reps", type=int, default=50, help="operator applications per timed step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-config5", action="store_true", help="skip the forty-layer adjoint record")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (HBM-counter calibration)")
@@ -361,9 +364,56 @@ def main():
         t32 = (out["time_to_U"].get("fp32_precond") or {}).get("time_to_U_s")
         if t64 and t32:
             out["time_to_U"]["speedup_fp32_precond"] = t64 / t32
+    if not args.no_solve and not args.no_config5:
+        del P, u64, u32, o64, o32
+        torch.cuda.empty_cache()
+        out["forty_layer_adjoint"] = forty_layer_adjoint(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def forty_layer_adjoint(log, reps=3):
+    """Untimed record on the forty-layer crystalline coating (8000 elements,
+    p = 5): setup, FP32-preconditioned solve, energies and the gradient of the
+    coating energy with respect to all forty coating thicknesses (one adjoint
+    solve plus the forty parameter derivatives); medians of `reps` passes."""
+    import torch
+    import paper_2111_06893_amd as dgtn
+    spec = W.config5()
+    n_coat = len(spec["layers"]) - 1
+    t0 = time.perf_counter()
+    P = dgtn.Problem(spec)
+    o = dgtn.default_opts(32, rtol=5e-8, max_iter=2000)
+    P.bind(o)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    w = np.r_[np.ones(n_coat), 0.0]
+    params = [("thickness", k) for k in range(n_coat)]
+    recs = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, st = P.solve(opts=o, raise_on_noconv=False)
+        U = P.energy(u)
+        t1 = time.perf_counter()
+        lam, st2 = P.solve(b=P.energy_grad(u, w), opts=o, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g = P.grad(u, lam, params, w)
+        t3 = time.perf_counter()
+        recs.append((t1 - t0, t2 - t1, t3 - t2, st.iters, st2.iters))
+    med = np.median(np.array(recs), axis=0)
+    log(f"forty-layer coating: setup {setup_s:.2f} s, solve {med[0] * 1e3:.1f} ms ({int(med[3])} it), "
+        f"adjoint solve {med[1] * 1e3:.1f} ms, 40 derivatives {med[2] * 1e3:.1f} ms")
+    rec = {"workload": "forty 1e-5 R cubic-crystal layers on fused silica, 8000 hex elements, p=5, "
+                       f"{W.n_dof(spec)} DoF",
+           "setup_s": setup_s, "solve_ms": med[0] * 1e3, "solve_iters": int(med[3]),
+           "adjoint_solve_ms": med[1] * 1e3, "adjoint_iters": int(med[4]),
+           "n_params": n_coat, "derivatives_ms": med[2] * 1e3,
+           "U_coat": float(np.sum(U[:n_coat])), "dUcoat_dd_first_last": [float(g[0]), float(g[-1])]}
+    P.close()
+    return rec
 
 
 def summarize_profiles(prof_dir, commands):

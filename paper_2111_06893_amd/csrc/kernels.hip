@@ -94,7 +94,17 @@ __global__ __launch_bounds__(line_threads<N>(), 7) void k_apply(LevelView<R> L, 
     // node role
     const bool nact = tid < N3;
     const int i = tid % N, j = (tid / N) % N, k = tid / N2;
-    const NodeGeo<R> g = nact ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
+    // node metric: held in registers in FP32; in FP64, where registers bound the
+    // occupancy, loaded again (from cache) by the two phases that use it
+    constexpr bool kReloadGeo = sizeof(R) == 8;
+    NodeGeo<R> g_held{1, 0, 0, 1, 1, 1};
+    if constexpr (!kReloadGeo) {
+        if (nact) g_held = node_geo<N>(L, col, iz, i, j);
+    }
+    auto node_metric = [&]() {
+        if constexpr (kReloadGeo) return node_geo<N>(L, col, iz, i, j);
+        else return g_held;
+    };
     // face role
     const bool fact = tid < 6 * N2;
     const int f = tid / N2, fi = tid % N2;
@@ -124,6 +134,7 @@ __global__ __launch_bounds__(line_threads<N>(), 7) void k_apply(LevelView<R> L, 
     // Only this lane reads its node's derivatives, so S is parked in those slots.
     const bool fxi = (i == 0) | (i == N - 1), feta = (j == 0) | (j == N - 1), fzeta = (k == 0) | (k == N - 1);
     if (nact) {
+        const NodeGeo<R> g = node_metric();
         R G[3][3], T[6], S[6];
         node_gradient<N>(sG, tid, g, sown[4], G);
         sym_of(G, S);
@@ -219,6 +230,7 @@ __global__ __launch_bounds__(line_threads<N>(), 7) void k_apply(LevelView<R> L, 
         }
         R T[6];
         cubic_stress(c11, c12, c44, S, T);
+        const NodeGeo<R> g = node_metric();
         const R wJ = sw[i] * sw[j] * sw[k] * g.det2 * R(0.5) * sown[3];
         const R dz = sown[4];
         const R Tx[3] = {T[0], T[3], T[4]};
