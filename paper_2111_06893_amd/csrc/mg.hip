@@ -214,14 +214,16 @@ __global__ __launch_bounds__(nthreads<N>()) void k_col_bwd(int n_cols, int nzN, 
 
 // Gather of r = b - Ax (or b) onto the patches and forward x/y transform:
 // T[c][iz*N + k][col*P2 + b'*P + a'] = sum_{a,b} Sx[a][a'] Sy[b][b'] r_patch[c][k][b][a].
-template <int N, typename R>
-__global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, const int* __restrict__ pg,
+// P = N + 2 overlap is a template parameter: every index split below is by a
+// compile-time constant and the transform loops unroll.
+template <int N, int P, typename R>
+__global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, const int* __restrict__ pg,
                                                  const R* __restrict__ wsq, const R* __restrict__ S,
                                                  const R* __restrict__ b, const R* __restrict__ Ax,
                                                  R* __restrict__ T) {
     constexpr int N2 = N * N, N3 = N2 * N;
     extern __shared__ char smem[];
-    const int P2 = P * P, NP = 3 * N * P2;
+    constexpr int P2 = P * P, NP = 3 * N * P2;
     R* sr = reinterpret_cast<R*>(smem);
     R* st = sr + NP;
     R* sS = st + NP;
@@ -242,6 +244,7 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, con
     for (int q = tid; q < NP; q += blockDim.x) {  // x: st[c][k][b][a'] = sum_a Sx[a][a'] sr[c][k][b][a]
         const int row = q / P, a2 = q % P;
         R acc = 0;
+#pragma unroll
         for (int a = 0; a < P; ++a) acc += sS[a * P + a2] * sr[row * P + a];
         st[q] = acc;
     }
@@ -252,17 +255,18 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, int P, con
         const R* sy = sS + P2;
         const R* src = st + (size_t)(c * N + k) * P2;
         R acc = 0;
+#pragma unroll
         for (int bb = 0; bb < P; ++bb) acc += sy[bb * P + b2] * src[bb * P + a2];
         T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab] = acc;
     }
 }
 
 // Backward x/y transform in place: T[..][col*P2 + b*P + a] = sum Sx[a][a'] Sy[b][b'] T[..][b'*P + a'].
-template <int N, typename R>
-__global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, int P, const R* __restrict__ S,
+template <int N, int P, typename R>
+__global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, const R* __restrict__ S,
                                                  R* __restrict__ T) {
     extern __shared__ char smem[];
-    const int P2 = P * P, NP = 3 * N * P2;
+    constexpr int P2 = P * P, NP = 3 * N * P2;
     R* sr = reinterpret_cast<R*>(smem);
     R* st = sr + NP;
     R* sS = st + NP;
@@ -280,6 +284,7 @@ __global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, int P, con
         const R* sy = sS + P2;
         const R* src = sr + (size_t)row * P2;
         R acc = 0;
+#pragma unroll
         for (int b2 = 0; b2 < P; ++b2) acc += sy[bb * P + b2] * src[b2 * P + a2];
         st[q] = acc;
     }
@@ -288,6 +293,7 @@ __global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, int P, con
         const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2, aa = ab % P;
         const R* src = st + (size_t)q - aa;
         R acc = 0;
+#pragma unroll
         for (int a2 = 0; a2 < P; ++a2) acc += sS[aa * P + a2] * src[a2];
         T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab] = acc;
     }
@@ -805,6 +811,18 @@ hipError_t dispatch(int N, F&& f) {
     }
 }
 
+// Patch width P = N + 2 overlap, overlap 0..3, as a compile-time constant.
+template <int N, typename F>
+hipError_t dispatch_patch(int P, F&& f) {
+    switch (P - N) {
+        case 0: return f(std::integral_constant<int, N>{});
+        case 2: return f(std::integral_constant<int, N + 2>{});
+        case 4: return f(std::integral_constant<int, N + 4>{});
+        case 6: return f(std::integral_constant<int, N + 6>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 template <typename R>
@@ -846,8 +864,11 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
     const size_t shm = sizeof(R) * (size_t)(2 * 3 * N * P * P + 2 * P * P);
     hipError_t err = dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_ovl_fwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, pg, wsq, S, b, Ax, T);
-        return hipGetLastError();
+        return dispatch_patch<NN>(P, [&](auto pp) {
+            constexpr int PP = decltype(pp)::value;
+            hipLaunchKernelGGL((k_ovl_fwd<NN, PP, R>), dim3(E), dim3(256), shm, s, n_cols, n, pg, wsq, S, b, Ax, T);
+            return hipGetLastError();
+        });
     });
     if (err != hipSuccess) return err;
     const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
@@ -856,7 +877,12 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_ovl_bwd<NN, R>), dim3(E), dim3(256), shm, s, n_cols, n, P, S, T);
+        const hipError_t e = dispatch_patch<NN>(P, [&](auto pp) {
+            constexpr int PP = decltype(pp)::value;
+            hipLaunchKernelGGL((k_ovl_bwd<NN, PP, R>), dim3(E), dim3(256), shm, s, n_cols, n, S, T);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
         const size_t tot = (size_t)E * 3 * NN * NN * NN;
         hipLaunchKernelGGL((k_ovl_sum<NN, R>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, n_cols, n_z, P, ps, wsq,
                            T, x, omega, Ax ? 1 : 0);
