@@ -353,8 +353,10 @@ template <> struct MfmaAcc<float> {
 };
 
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
-template <typename R>
-__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, int trans, const R* __restrict__ V,
+// W: patch width (the eigenvalue division of trans = 1 splits the column index by
+// W and W^2, compile-time constants here); trans = 0 takes W = 0.
+template <typename R, int W, int trans>
+__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ V,
                                                        const R* __restrict__ in, R* __restrict__ out,
                                                        const R* __restrict__ lz, const R* __restrict__ lam,
                                                        const R* __restrict__ rat) {
@@ -375,8 +377,8 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, i
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
             int kk, rr;
-            if (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
-            else { rr = q / kGK; kk = q % kGK; }         // V[row][k]: k contiguous
+            if constexpr (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
+            else { rr = q / kGK; kk = q % kGK; }                   // V[row][k]: k contiguous
             const int kg = k0 + kk, rg = row0 + rr;
             ra[t] = (kg < n && rg < n) ? (trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg]) : R(0);
         }
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, i
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
-            if (trans) As[q / kGM][q % kGM] = ra[t];
+            if constexpr (trans) As[q / kGM][q % kGM] = ra[t];
             else As[q % kGK][q / kGK] = ra[t];
         }
 #pragma unroll
@@ -422,7 +424,6 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, i
         }
         __syncthreads();
     }
-    const int N2 = N * N;
     R* Oc = out + (size_t)c * n * ncol;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -430,15 +431,19 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, int N, i
         for (int b = 0; b < 2; ++b) {
             const int cg = col0 + wc + 16 * b + lane % 16;
             if (cg >= ncol) continue;
-            const int colm = cg / N2, ab = cg % N2, bb = ab / N, aa = ab % N;
-            const R lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * N + aa] +
-                          rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * N + bb];
+            R lxy = 0;
+            if constexpr (trans) {
+                constexpr int W2 = W * W;
+                const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
+                lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
+                      rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rg = row0 + wr + 16 * a + Acc::row(lane, q);
                 if (rg >= n) continue;
                 R v = acc[a][b][q];
-                if (trans) v /= lz[(size_t)c * n + rg] + lxy;
+                if constexpr (trans) v /= lz[(size_t)c * n + rg] + lxy;
                 Oc[(size_t)rg * ncol + cg] = v;
             }
         }
@@ -811,6 +816,38 @@ hipError_t dispatch(int N, F&& f) {
     }
 }
 
+// Both z-products of one smoother application: Y = (V^T T) / (lz + lxy), then T = V Y.
+template <typename R>
+hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
+                         hipStream_t s) {
+    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
+    hipError_t err = hipErrorInvalidValue;
+    auto fwd = [&](auto w) {
+        constexpr int WW = decltype(w)::value;
+        hipLaunchKernelGGL((k_col_gemm_mfma<R, WW, 1>), grid, dim3(256), 0, s, n, ncol, V, T, Y, lz, lam, rat);
+        return hipGetLastError();
+    };
+    switch (W) {
+        case 2: err = fwd(std::integral_constant<int, 2>{}); break;
+        case 3: err = fwd(std::integral_constant<int, 3>{}); break;
+        case 4: err = fwd(std::integral_constant<int, 4>{}); break;
+        case 5: err = fwd(std::integral_constant<int, 5>{}); break;
+        case 6: err = fwd(std::integral_constant<int, 6>{}); break;
+        case 7: err = fwd(std::integral_constant<int, 7>{}); break;
+        case 8: err = fwd(std::integral_constant<int, 8>{}); break;
+        case 9: err = fwd(std::integral_constant<int, 9>{}); break;
+        case 10: err = fwd(std::integral_constant<int, 10>{}); break;
+        case 11: err = fwd(std::integral_constant<int, 11>{}); break;
+        case 12: err = fwd(std::integral_constant<int, 12>{}); break;
+        case 13: err = fwd(std::integral_constant<int, 13>{}); break;
+        case 14: err = fwd(std::integral_constant<int, 14>{}); break;
+        default: break;
+    }
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_col_gemm_mfma<R, 0, 0>), grid, dim3(256), 0, s, n, ncol, V, Y, T, lz, lam, rat);
+    return hipGetLastError();
+}
+
 // Patch width P = N + 2 overlap, overlap 0..3, as a compile-time constant.
 template <int N, typename F>
 hipError_t dispatch_patch(int P, F&& f) {
@@ -844,10 +881,7 @@ hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, c
         return hipGetLastError();
     });
     if (err != hipSuccess) return err;
-    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
-    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, N, 1, V, T, Y, lz, lam, rat);
-    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, N, 0, V, Y, T, lz, lam, rat);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = col_gemm_pair<R>(N, n, ncol, V, T, Y, lz, lam, rat, s)) != hipSuccess) return err;
     return dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         hipLaunchKernelGGL((k_col_bwd<NN, R>), dim3(E), dim3(nthreads<NN>()), 0, s, n_cols, n, S, T, x, omega,
@@ -871,10 +905,7 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
         });
     });
     if (err != hipSuccess) return err;
-    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
-    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, P, 1, V, T, Y, lz, lam, rat);
-    hipLaunchKernelGGL((k_col_gemm_mfma<R>), grid, dim3(256), 0, s, n, ncol, P, 0, V, Y, T, lz, lam, rat);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = col_gemm_pair<R>(P, n, ncol, V, T, Y, lz, lam, rat, s)) != hipSuccess) return err;
     return dispatch(N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         const hipError_t e = dispatch_patch<NN>(P, [&](auto pp) {
