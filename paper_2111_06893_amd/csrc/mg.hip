@@ -450,12 +450,15 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
 }
 
 // Fine += P coarse over the same elements, P = I (x) I (x) I with I [Nf][Nc].
-template <typename R>
-__global__ void k_prolong_p(int E, int Nf, int Nc, const R* __restrict__ I, const R* __restrict__ uc,
+// NF, NC: the sizes as compile-time constants (the pairs p -> max(1, p / 2)
+// produces), or 0 to take them from the arguments.
+template <typename R, int NF, int NC>
+__global__ void k_prolong_p(int E, int Nf_, int Nc_, const R* __restrict__ I, const R* __restrict__ uc,
                             R* __restrict__ uf) {
     __shared__ R s[3 * kMaxN * kMaxN * kMaxN];
     __shared__ R t[3 * kMaxN * kMaxN * kMaxN];
     __shared__ R sI[kMaxN * kMaxN];
+    const int Nf = NF ? NF : Nf_, Nc = NC ? NC : Nc_;
     const int e = blockIdx.x, tid = threadIdx.x;
     const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
     for (int q = tid; q < 3 * Nc3; q += blockDim.x) s[q] = uc[(size_t)e * 3 * Nc3 + q];
@@ -486,12 +489,13 @@ __global__ void k_prolong_p(int E, int Nf, int Nc, const R* __restrict__ I, cons
 }
 
 // Coarse = P^T fine.
-template <typename R>
-__global__ void k_restrict_p(int E, int Nf, int Nc, const R* __restrict__ I, const R* __restrict__ rf,
+template <typename R, int NF, int NC>
+__global__ void k_restrict_p(int E, int Nf_, int Nc_, const R* __restrict__ I, const R* __restrict__ rf,
                              R* __restrict__ rc) {
     __shared__ R s[3 * kMaxN * kMaxN * kMaxN];
     __shared__ R t[3 * kMaxN * kMaxN * kMaxN];
     __shared__ R sI[kMaxN * kMaxN];
+    const int Nf = NF ? NF : Nf_, Nc = NC ? NC : Nc_;
     const int e = blockIdx.x, tid = threadIdx.x;
     const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
     for (int q = tid; q < 3 * Nf3; q += blockDim.x) s[q] = rf[(size_t)e * 3 * Nf3 + q];
@@ -848,6 +852,20 @@ hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R
     return hipGetLastError();
 }
 
+// (Nf, Nc) pairs of the p-coarsening as compile-time constants; other pairs run
+// the kernels with runtime sizes.
+template <typename F>
+hipError_t dispatch_pair(int Nf, int Nc, F&& f) {
+    using std::integral_constant;
+    if (Nf == 8 && Nc == 4) return f(integral_constant<int, 8>{}, integral_constant<int, 4>{});
+    if (Nf == 7 && Nc == 4) return f(integral_constant<int, 7>{}, integral_constant<int, 4>{});
+    if (Nf == 6 && Nc == 3) return f(integral_constant<int, 6>{}, integral_constant<int, 3>{});
+    if (Nf == 5 && Nc == 3) return f(integral_constant<int, 5>{}, integral_constant<int, 3>{});
+    if (Nf == 4 && Nc == 2) return f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
+    if (Nf == 3 && Nc == 2) return f(integral_constant<int, 3>{}, integral_constant<int, 2>{});
+    return f(integral_constant<int, 0>{}, integral_constant<int, 0>{});
+}
+
 // Patch width P = N + 2 overlap, overlap 0..3, as a compile-time constant.
 template <int N, typename F>
 hipError_t dispatch_patch(int P, F&& f) {
@@ -935,14 +953,20 @@ hipError_t mg_restrict_z(int N, int Ec, int n_cols, const int* zch, const R* Iz,
 
 template <typename R>
 hipError_t mg_prolong_p(int E, int Nf, int Nc, const R* I, const R* uc, R* uf, hipStream_t s) {
-    hipLaunchKernelGGL((k_prolong_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, uc, uf);
-    return hipGetLastError();
+    return dispatch_pair(Nf, Nc, [&](auto f, auto c) {
+        hipLaunchKernelGGL((k_prolong_p<R, decltype(f)::value, decltype(c)::value>), dim3(E), dim3(256), 0, s, E, Nf,
+                           Nc, I, uc, uf);
+        return hipGetLastError();
+    });
 }
 
 template <typename R>
 hipError_t mg_restrict_p(int E, int Nf, int Nc, const R* I, const R* rf, R* rc, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict_p<R>), dim3(E), dim3(256), 0, s, E, Nf, Nc, I, rf, rc);
-    return hipGetLastError();
+    return dispatch_pair(Nf, Nc, [&](auto f, auto c) {
+        hipLaunchKernelGGL((k_restrict_p<R, decltype(f)::value, decltype(c)::value>), dim3(E), dim3(256), 0, s, E, Nf,
+                           Nc, I, rf, rc);
+        return hipGetLastError();
+    });
 }
 
 template <typename R>
