@@ -527,10 +527,11 @@ __global__ void k_restrict_p(int E, int Nf_, int Nc_, const R* __restrict__ I, c
 
 // h-transfers.  Ih [2][N][N]: Ih[s][a][b] = l_b(child-s node a in parent coordinates).
 // Fine element e_f = iz * ncf + colf; parent[colf] = coarse column, child[colf] = sx + 2 sy.
-template <typename R>
-__global__ void k_prolong_h(int N, int ncf, int ncc, const int* __restrict__ parent,
+template <typename R, int NT>
+__global__ void k_prolong_h(int N_, int ncf, int ncc, const int* __restrict__ parent,
                             const int* __restrict__ child, const R* __restrict__ Ih, const R* __restrict__ uc,
                             R* __restrict__ uf) {
+    const int N = NT ? NT : N_;  // NT: N as a compile-time constant, or 0
     const int ef = blockIdx.x, tid = threadIdx.x;
     const int colf = ef % ncf, iz = ef / ncf;
     const int ec = iz * ncc + parent[colf];
@@ -555,9 +556,10 @@ __global__ void k_prolong_h(int N, int ncf, int ncc, const int* __restrict__ par
 // merged in pairs; an unpaired last element is carried over).  Iz[izf][k][kk] is
 // coarse basis function kk at node k of fine z-element izf, zpar[izf] its coarse
 // element, zch[izc][2] the fine elements of coarse element izc (-1 if none).
-template <typename R>
-__global__ void k_prolong_z(int N, int n_cols, const int* __restrict__ zpar, const R* __restrict__ Iz,
+template <typename R, int NT>
+__global__ void k_prolong_z(int N_, int n_cols, const int* __restrict__ zpar, const R* __restrict__ Iz,
                             const R* __restrict__ uc, R* __restrict__ uf) {
+    const int N = NT ? NT : N_;  // NT: N as a compile-time constant, or 0
     const int ef = blockIdx.x, tid = threadIdx.x;
     const int col = ef % n_cols, izf = ef / n_cols;
     const size_t ec = (size_t)zpar[izf] * n_cols + col;
@@ -572,9 +574,10 @@ __global__ void k_prolong_z(int N, int n_cols, const int* __restrict__ zpar, con
     }
 }
 
-template <typename R>
-__global__ void k_restrict_z(int N, int n_cols, const int* __restrict__ zch, const R* __restrict__ Iz,
+template <typename R, int NT>
+__global__ void k_restrict_z(int N_, int n_cols, const int* __restrict__ zch, const R* __restrict__ Iz,
                              const R* __restrict__ rf, R* __restrict__ rc) {
+    const int N = NT ? NT : N_;  // NT: N as a compile-time constant, or 0
     const int ec = blockIdx.x, tid = threadIdx.x;
     const int col = ec % n_cols, izc = ec / n_cols;
     const int N2 = N * N, N3 = N2 * N;
@@ -592,9 +595,10 @@ __global__ void k_restrict_z(int N, int n_cols, const int* __restrict__ zch, con
     }
 }
 
-template <typename R>
-__global__ void k_restrict_h(int N, int ncf, int ncc, const int* __restrict__ children,
+template <typename R, int NT>
+__global__ void k_restrict_h(int N_, int ncf, int ncc, const int* __restrict__ children,
                              const R* __restrict__ Ih, const R* __restrict__ rf, R* __restrict__ rc) {
+    const int N = NT ? NT : N_;  // NT: N as a compile-time constant, or 0
     const int ec = blockIdx.x, tid = threadIdx.x;
     const int colc = ec % ncc, iz = ec / ncc;
     const int N2 = N * N, N3 = N2 * N;
@@ -941,14 +945,20 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
 
 template <typename R>
 hipError_t mg_prolong_z(int N, int Ef, int n_cols, const int* zpar, const R* Iz, const R* uc, R* uf, hipStream_t s) {
-    hipLaunchKernelGGL((k_prolong_z<R>), dim3(Ef), dim3(256), 0, s, N, n_cols, zpar, Iz, uc, uf);
-    return hipGetLastError();
+    return dispatch(N, [&](auto nn) {
+        hipLaunchKernelGGL((k_prolong_z<R, decltype(nn)::value>), dim3(Ef), dim3(256), 0, s, N, n_cols, zpar, Iz, uc,
+                           uf);
+        return hipGetLastError();
+    });
 }
 
 template <typename R>
 hipError_t mg_restrict_z(int N, int Ec, int n_cols, const int* zch, const R* Iz, const R* rf, R* rc, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict_z<R>), dim3(Ec), dim3(256), 0, s, N, n_cols, zch, Iz, rf, rc);
-    return hipGetLastError();
+    return dispatch(N, [&](auto nn) {
+        hipLaunchKernelGGL((k_restrict_z<R, decltype(nn)::value>), dim3(Ec), dim3(256), 0, s, N, n_cols, zch, Iz, rf,
+                           rc);
+        return hipGetLastError();
+    });
 }
 
 template <typename R>
@@ -972,15 +982,21 @@ hipError_t mg_restrict_p(int E, int Nf, int Nc, const R* I, const R* rf, R* rc, 
 template <typename R>
 hipError_t mg_prolong_h(int N, int Ef, int ncf, int ncc, const int* parent, const int* child, const R* Ih,
                         const R* uc, R* uf, hipStream_t s) {
-    hipLaunchKernelGGL((k_prolong_h<R>), dim3(Ef), dim3(256), 0, s, N, ncf, ncc, parent, child, Ih, uc, uf);
-    return hipGetLastError();
+    return dispatch(N, [&](auto nn) {
+        hipLaunchKernelGGL((k_prolong_h<R, decltype(nn)::value>), dim3(Ef), dim3(256), 0, s, N, ncf, ncc, parent,
+                           child, Ih, uc, uf);
+        return hipGetLastError();
+    });
 }
 
 template <typename R>
 hipError_t mg_restrict_h(int N, int Ec, int ncf, int ncc, const int* children, const R* Ih, const R* rf, R* rc,
                          hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict_h<R>), dim3(Ec), dim3(256), 0, s, N, ncf, ncc, children, Ih, rf, rc);
-    return hipGetLastError();
+    return dispatch(N, [&](auto nn) {
+        hipLaunchKernelGGL((k_restrict_h<R, decltype(nn)::value>), dim3(Ec), dim3(256), 0, s, N, ncf, ncc, children,
+                           Ih, rf, rc);
+        return hipGetLastError();
+    });
 }
 
 hipError_t dense_set_unit(double* e, int j, hipStream_t s) {
