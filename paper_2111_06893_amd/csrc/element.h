@@ -249,12 +249,13 @@ __device__ __forceinline__ void face_node(int f, int fi, int& i, int& j, int& k)
 }
 
 // Lanes of the operator kernels: 9 N^2 line tasks (3 directions x 3 components
-// x N^2 lines), N^3 nodes, 6 N^2 face nodes, rounded up to whole waves.
+// x N^2 lines), N^3 nodes, 6 N^2 face nodes, rounded up to an even number of
+// waves: a CU holds three workgroups of seven waves but four of eight (measured).
 template <int N>
 constexpr int line_threads() {
     constexpr int a = 9 * N * N, b = N * N * N, c = 6 * N * N;
     constexpr int m = a > b ? (a > c ? a : c) : (b > c ? b : c);
-    return ((m + 63) / 64) * 64;
+    return ((m + 127) / 128) * 128;
 }
 
 // Line task t < 9 N^2: direction d (xi, eta, zeta), component c, and the offset

@@ -61,11 +61,12 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     dst[2 * N2] = t[2];
 }
 
-// Seven waves per SIMD: with the FP64 lift factors stored over u (below) the
-// LDS of four workgroups fits a CU at N = 7 (40.5 KB each), at the cost of a few
-// spilled registers; measured faster than three workgroups.
+// Waves per SIMD: eight in FP32 (four workgroups of eight waves per CU); seven
+// in FP64, whose 68 registers do not fit eight without spills (measured no
+// faster at 2000 elements, and the spill traffic goes to HBM).  The FP64 lift
+// factors are stored over u (below), which keeps the LDS at 40.5 KB for N = 7.
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>(), 7) void k_apply(LevelView<R> L, const R* __restrict__ u,
+__global__ __launch_bounds__(line_threads<N>(), sizeof(R) == 4 ? 8 : 7) void k_apply(LevelView<R> L, const R* __restrict__ u,
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
