@@ -220,12 +220,16 @@ __device__ __forceinline__ void load_faces(const LevelView<R>& L, int col, int i
         fi.f = nb.f;
         fi.flip = nb.flip;
         fi.bc = nb.bc;
+        // the neighbour's z-element index does not wait for the column tables: a side
+        // neighbour lies in the same z-layer, a z-neighbour one layer up or down
+        const int izn = tid < 4 ? iz : (tid == 4 ? max(iz - 1, 0) : min(iz + 1, L.n_z - 1));
         const int m = L.zmat[iz];
-        const int mn = nb.bc == 0 ? L.zmat[nb.e / L.n_cols] : m;
-        fi.c11 = R(0.5) * (L.mat[3 * m] + L.mat[3 * mn]);
-        fi.c12 = R(0.5) * (L.mat[3 * m + 1] + L.mat[3 * mn + 1]);
-        fi.c44 = R(0.5) * (L.mat[3 * m + 2] + L.mat[3 * mn + 2]);
-        fi.hz = nb.bc == 0 ? L.hz[nb.e / L.n_cols] : L.hz[iz];
+        const int mn = L.zmat[izn];
+        const bool in = nb.bc == 0;
+        fi.c11 = R(0.5) * (L.mat[3 * m] + L.mat[3 * (in ? mn : m)]);
+        fi.c12 = R(0.5) * (L.mat[3 * m + 1] + L.mat[3 * (in ? mn : m) + 1]);
+        fi.c44 = R(0.5) * (L.mat[3 * m + 2] + L.mat[3 * (in ? mn : m) + 2]);
+        fi.hz = in ? L.hz[izn] : L.hz[iz];
         fi.sig = L.penalty_n2 / min(fi.hz, L.hz[iz]);
         sf[tid] = fi;
     } else if (tid == 6) {
