@@ -71,6 +71,18 @@ struct SolverState {
     double* host_mon = nullptr;
     hipEvent_t mon_event[2] = {nullptr, nullptr};
     dgtn_status host_monitor();
+    // V-cycles recorded once as HIP graphs (per precision and smoother setting) on a
+    // private stream and replayed on the caller's stream: one launch instead of one
+    // per kernel.  They hold workspace addresses, so binding drops them.
+    struct VGraph {
+        int prec, nu, smoother;
+        double omega;
+        hipGraphExec_t exec;
+    };
+    std::vector<VGraph> vgraphs;
+    hipStream_t cap_stream = nullptr;
+    bool graphs_off = std::getenv("DGTN_NO_GRAPHS") != nullptr;  // eager V-cycles (for comparison)
+    void drop_graphs();
     ~SolverState();
 };
 
@@ -946,6 +958,7 @@ dgtn_status upload(dgtn_ctx* c, size_t off, const void* src, size_t bytes, hipSt
 
 dgtn_status bind_solver(dgtn_ctx* c, hipStream_t s) {
     SolverState& S = *c->solver;
+    S.drop_graphs();
     if (!S.planned) return DGTN_OK;
     std::vector<std::vector<float>> keep;
     auto up2 = [&](const size_t off[2], const std::vector<double>& v) -> dgtn_status {
@@ -1087,6 +1100,46 @@ dgtn_status vcycle(dgtn_ctx* c, int l, const VOpts& o, hipStream_t s) {
     return DGTN_OK;
 }
 
+// The level-0 V-cycle (b -> x in the level-0 workspace buffers) on stream s: the
+// recorded graph for this precision and smoother setting, recorded on first use.
+// If recording fails, V-cycles run eagerly from then on.
+dgtn_status vcycle_launch(dgtn_ctx* c, int prec, const VOpts& o, hipStream_t s) {
+    SolverState& S = *c->solver;
+    auto eager = [&]() { return prec == 32 ? vcycle<float>(c, 0, o, s) : vcycle<double>(c, 0, o, s); };
+    if (S.graphs_off) return eager();
+    for (const auto& g : S.vgraphs)
+        if (g.prec == prec && g.nu == o.nu && g.smoother == o.smoother && g.omega == o.omega) {
+            SHIP(hipGraphLaunch(g.exec, s));
+            return DGTN_OK;
+        }
+    if (!S.cap_stream && hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        S.graphs_off = true;
+        return eager();
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        S.graphs_off = true;
+        return eager();
+    }
+    const dgtn_status st = prec == 32 ? vcycle<float>(c, 0, o, S.cap_stream) : vcycle<double>(c, 0, o, S.cap_stream);
+    const hipError_t ec = hipStreamEndCapture(S.cap_stream, &graph);
+    if (st != DGTN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    const bool ok = ec == hipSuccess && graph && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+        S.graphs_off = true;
+        return eager();
+    }
+    S.vgraphs.push_back({prec, o.nu, o.smoother, o.omega, exec});
+    SHIP(hipGraphLaunch(exec, s));
+    return DGTN_OK;
+}
+
 // z = M^{-1} v in the preconditioner's precision (v, z FP64).
 dgtn_status precondition(dgtn_ctx* c, int prec, const VOpts& o, const double* v, double* z, hipStream_t s) {
     SolverState& S = *c->solver;
@@ -1097,12 +1150,12 @@ dgtn_status precondition(dgtn_ctx* c, int prec, const VOpts& o, const double* v,
     }
     if (prec == 32) {
         SHIP(vec_cast<double, float>(v, at<float>(c, S.mg[0].off_b[1]), n, 1.0, s));
-        dgtn_status st = vcycle<float>(c, 0, o, s);
+        dgtn_status st = vcycle_launch(c, 32, o, s);
         if (st != DGTN_OK) return st;
         SHIP(vec_cast<float, double>(at<float>(c, S.mg[0].off_x[1]), z, n, 1.0, s));
     } else {
         SHIP(vec_cast<double, double>(v, at<double>(c, S.mg[0].off_b[0]), n, 1.0, s));
-        dgtn_status st = vcycle<double>(c, 0, o, s);
+        dgtn_status st = vcycle_launch(c, 64, o, s);
         if (st != DGTN_OK) return st;
         SHIP(vec_cast<double, double>(at<double>(c, S.mg[0].off_x[0]), z, n, 1.0, s));
     }
@@ -1149,7 +1202,14 @@ dgtn_status dgtn::SolverState::host_monitor() {
     return DGTN_OK;
 }
 
+void dgtn::SolverState::drop_graphs() {
+    for (auto& g : vgraphs) (void)hipGraphExecDestroy(g.exec);
+    vgraphs.clear();
+}
+
 dgtn::SolverState::~SolverState() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : mon_event)
         if (e) (void)hipEventDestroy(e);
     if (host_mon) (void)hipHostFree(host_mon);
