@@ -19,13 +19,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <exception>
 #include <cmath>
 #include <limits>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "context.h"
@@ -202,6 +206,7 @@ void build_fdm(const dgtn_ctx* c, const Level& L, std::vector<double>& out) {
         c12 = mc[3 * m + 1] / yr;
         c44 = mc[3 * m + 2] / yr;
     };
+    std::map<std::array<double, 6>, std::vector<double>> solved;
     for (int col = 0; col < L.n_cols; ++col) {
         const double* gg = &L.geo2[(size_t)col * 5 * N2];
         // mean widths and axis directions of the column in the xy-plane
@@ -265,9 +270,18 @@ void build_fdm(const dgtn_ctx* c, const Level& L, std::vector<double>& out) {
                     const double kappa = kap(m);
                     const double rlo = mlo >= 0 ? 0.5 * (kappa + kap(mlo)) / kappa : 1.0;
                     const double rhi = mhi >= 0 ? 0.5 * (kappa + kap(mhi)) / kappa : 1.0;
-                    auto K = element_1d(L.lgl, h, lo, slo * rlo, hi, shi * rhi);
                     double* blk = fe + (cc * 3 + d) * PER;
-                    fdm_1d(L.lgl, h, K, blk, blk + N2, kappa);
+                    // many elements share the same 1D problem (a column's widths, a layer's
+                    // thickness and material): solve each distinct one once
+                    const std::array<double, 6> key{h, (double)lo, slo * rlo, (double)hi, shi * rhi, kappa};
+                    auto it = solved.find(key);
+                    if (it == solved.end()) {
+                        auto K = element_1d(L.lgl, h, lo, slo * rlo, hi, shi * rhi);
+                        std::vector<double> res(PER);
+                        fdm_1d(L.lgl, h, K, res.data(), res.data() + N2, kappa);
+                        it = solved.emplace(key, std::move(res)).first;
+                    }
+                    std::copy(it->second.begin(), it->second.end(), blk);
                 }
             }
         }
@@ -332,7 +346,11 @@ void sym_eigen(int n, std::vector<double> A, std::vector<double>& Q, std::vector
     std::vector<double> e(n, 0.0);
     for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
     for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
-    // implicit QL on the tridiagonal (d, e), rotations accumulated into Q
+    // implicit QL on the tridiagonal (d, e), rotations accumulated into Q held
+    // transposed (each rotation then updates two contiguous rows)
+    std::vector<double> QT((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) QT[(size_t)k * n + i] = Q[(size_t)i * n + k];
     for (int l = 0; l < n; ++l) {
         for (int iter = 0; iter < 200; ++iter) {
             int m = l;
@@ -362,10 +380,12 @@ void sym_eigen(int n, std::vector<double> A, std::vector<double>& Q, std::vector
                 pp = s * r;
                 d[i + 1] = g + pp;
                 g = cth * r - b;
+                double* qi = &QT[(size_t)i * n];
+                double* qj = &QT[(size_t)(i + 1) * n];
                 for (int k = 0; k < n; ++k) {
-                    const double qa = Q[(size_t)k * n + i + 1];
-                    Q[(size_t)k * n + i + 1] = s * Q[(size_t)k * n + i] + cth * qa;
-                    Q[(size_t)k * n + i] = cth * Q[(size_t)k * n + i] - s * qa;
+                    const double qa = qj[k];
+                    qj[k] = s * qi[k] + cth * qa;
+                    qi[k] = cth * qi[k] - s * qa;
                 }
             }
             if (r == 0.0 && i >= l) continue;
@@ -374,6 +394,8 @@ void sym_eigen(int n, std::vector<double> A, std::vector<double>& Q, std::vector
             e[m] = 0.0;
         }
     }
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) Q[(size_t)i * n + k] = QT[(size_t)k * n + i];
 }
 
 // The 1D DG operator of the scheme along a whole z-column for one component:
@@ -663,12 +685,8 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
     for (int e = 0; e < nz; ++e)
         for (int k = 0; k < N; ++k)
             ms[e * N + k] = 1.0 / std::sqrt(level_mat(c, L)[3 * L.zmat[e] + 2] / yr * L.lgl.w[k] * 0.5 * L.hz[e]);
-    for (int cc = 0; cc < 3; ++cc) {
-        if (cc == 1) {  // same modulus along z as component 0
-            std::copy(out.V.begin(), out.V.begin() + (size_t)n * n, out.V.begin() + (size_t)n * n);
-            std::copy(out.Lz.begin(), out.Lz.begin() + n, out.Lz.begin() + n);
-            continue;
-        }
+    // components 0 (= 1, the same modulus along z) and 2 are independent: solved concurrently
+    auto solve_component = [&](int cc) {
         std::vector<double> kap(nz);
         for (int e = 0; e < nz; ++e) kap[e] = level_mat(c, L)[3 * L.zmat[e] + (cc == 2 ? 0 : 2)] / yr;
         auto K = column_1d(L.lgl, L.hz, kap, L.pen_z, c->prob.bc_top, c->prob.bc_bottom);
@@ -682,7 +700,12 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
             out.Lz[(size_t)cc * n + a] = std::max(d[a], 1e-14 * dmax);
             for (int i = 0; i < n; ++i) out.V[((size_t)cc * n + i) * n + a] = ms[i] * Q[(size_t)i * n + a];
         }
-    }
+    };
+    std::thread other(solve_component, 2);
+    solve_component(0);
+    other.join();
+    std::copy(out.V.begin(), out.V.begin() + (size_t)n * n, out.V.begin() + (size_t)n * n);
+    std::copy(out.Lz.begin(), out.Lz.begin() + n, out.Lz.begin() + n);
 }
 
 // ---- level hierarchy -----------------------------------------------------------
@@ -835,10 +858,24 @@ dgtn_status prepare_levels(dgtn_ctx* c, const dgtn_solve_opts* opts) {
     S.mg.assign(c->levels.size(), MgLevel{});
     S.tr.assign(c->levels.size() - 1, Transfer{});
     if (opts) {
+        // the levels' smoother data are independent: built concurrently, one thread per level
+        std::vector<ColumnData> cols(c->levels.size());
+        std::vector<std::exception_ptr> fail(c->levels.size());
+        std::vector<std::thread> workers;
+        for (size_t l = 0; l < c->levels.size(); ++l)
+            workers.emplace_back([&, l]() {
+                try {
+                    build_fdm(c, c->levels[l], S.mg[l].fdm);
+                    build_column(c, c->levels[l], opts->overlap, cols[l]);
+                } catch (...) {
+                    fail[l] = std::current_exception();
+                }
+            });
+        for (auto& t : workers) t.join();
+        for (auto& f : fail)
+            if (f) std::rethrow_exception(f);
         for (size_t l = 0; l < c->levels.size(); ++l) {
-            build_fdm(c, c->levels[l], S.mg[l].fdm);
-            ColumnData cd;
-            build_column(c, c->levels[l], opts->overlap, cd);
+            ColumnData& cd = cols[l];
             MgLevel& M = S.mg[l];
             M.P = cd.P;
             M.pg = std::move(cd.pg);
