@@ -164,7 +164,9 @@ dgtn_status dgtn_workspace_bytes(const dgtn_ctx* ctx, const dgtn_solve_opts* opt
 
 /* Binds a device workspace of `bytes` bytes (256-byte aligned) and uploads
  * the geometry into it on `stream`.  opts as in dgtn_workspace_bytes.  The
- * workspace must stay allocated until dgtn_destroy or the next dgtn_bind. */
+ * workspace must stay allocated until dgtn_destroy or the next dgtn_bind.
+ * Binding discards the V-cycles recorded as HIP graphs (dgtn_solve), which
+ * refer to the previous workspace.  Synchronises the stream. */
 dgtn_status dgtn_bind(dgtn_ctx* ctx, void* workspace, size_t bytes,
                       const dgtn_solve_opts* opts, hipStream_t stream);
 
@@ -201,7 +203,12 @@ dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double*
 /* z = M^{-1} v: one application of the solver's preconditioner (the V-cycle
  * of dgtn_solve with the same options, in opts->precond_precision), for the
  * operator scaled by 1 / y_ref.  v, z: device double arrays of n_dof values,
- * not aliased.  The workspace must have been bound with the same options. */
+ * not aliased.  The workspace must have been bound with the same options.
+ * Here and in dgtn_solve the V-cycle is recorded once (per precision and
+ * smoother setting) as a HIP graph on a stream the library owns and replayed
+ * on `stream`; with the environment variable DGTN_NO_GRAPHS set when the
+ * solver state is created, or if recording fails, it is launched kernel by
+ * kernel instead (same kernels, same results). */
 dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* v, double* z,
                               hipStream_t stream);
 
