@@ -331,7 +331,7 @@ def main():
         "config": {"workload": "thin-coating cylinder, 2000 hex elements, p=6, 2,058,000 DoF "
                                "(coating 1e-3 R, 140 GPa/0.23 on 72 GPa/0.17, 24 graded substrate elements)",
                    "n_dof": n_dof, "elements": W.n_elements(spec), "p": spec["p"],
-                   "applies_per_step": args.reps, "precond": "fp32 multigrid V-cycle (p- then h-coarsening, 5 levels) with weighted overlapping column-Schwarz smoother (overlap 1, damping 0.6), dense coarsest solve",
+                   "applies_per_step": args.reps, "precond": "fp32 multigrid V-cycle (p- then h-coarsening, 5 levels) with weighted overlapping column-Schwarz smoother (overlap 1, damping 0.65), dense coarsest solve",
                    "solve_rtol": rtol32},
         "step": {"apply_block_ms": a64 * args.reps * 1e3,
                  "solve_ms": float(np.median([r.get("solve_s", 0) for r in recs])) * 1e3,

@@ -120,7 +120,7 @@ def noise_psd_parts(U_parts, phi_parts, T, f, F0):
 
 def default_opts(precision=64, **kw):
     o = dict(precond_precision=precision, restart=30, max_iter=20000, rtol=1e-11,
-             mg_levels=16, smooth_steps=1, smooth_damping=0.6, smoother=1, krylov=1, overlap=1)
+             mg_levels=16, smooth_steps=1, smooth_damping=0.65, smoother=1, krylov=1, overlap=1)
     o.update(kw)
     return _lib.SolveOpts(**o)
 

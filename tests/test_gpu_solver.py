@@ -219,7 +219,7 @@ def test_overlapping_schwarz_cuts_iterations_and_keeps_the_energy(name):
 @pytest.mark.parametrize("prec", [64, 32])
 def test_multigrid_with_overlapping_smoother(prec):
     # default preconditioner: V-cycle over p- and h-coarsened levels, weighted
-    # overlapping column smoother (damping 0.6), dense coarsest solve
+    # overlapping column smoother (damping 0.65), dense coarsest solve
     g = _golden("config1")
     spec = g["spec"]
     P = dgtn.Problem(spec)
