@@ -33,7 +33,10 @@ hipError_t mg_restrict_h(int N, int Ec, int ncf, int ncc, const int* children, c
                          hipStream_t s);
 
 hipError_t dense_set_unit(double* e, int j, hipStream_t s);
-hipError_t dense_invert(double* A, double* col, int n, hipStream_t s);
+// In-place inverse of the n x n SPD matrix A (blocked Gauss-Jordan, no pivoting);
+// scratch: dense_invert_scratch(n) doubles of device memory.
+size_t dense_invert_scratch(int n);
+hipError_t dense_invert(double* A, double* scratch, int n, hipStream_t s);
 template <typename R>
 hipError_t dense_gemv(const R* A, const R* x, R* y, int n, hipStream_t s);
 

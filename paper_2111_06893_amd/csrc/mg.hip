@@ -629,30 +629,116 @@ __global__ void k_set_unit(double* e, int j) {
     }
 }
 
-// Gauss-Jordan step k on the n x n matrix A (in place -> inverse).  Stage 1
-// saves column k, stage 2 scales row k by 1/A[k][k] (A[k][k] replaced by 1).
-__global__ void k_gj_savecol(const double* A, double* col, int n, int k) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) col[j] = A[(size_t)j * n + k];
+// Blocked Gauss-Jordan inversion in place of the n x n SPD matrix A, without
+// pivoting (the Schur complements of an SPD matrix stay SPD), in column blocks
+// K = [k0, k0 + b) of width b <= kGJB:
+//   P = A_KK^-1,  R = P A_K*,  A_ij -= A_iK R_j (i, j not in K),
+//   A_iK = -A_iK P (i not in K),  A_K* = R (A_KK = P).
+constexpr int kGJB = 32;
+
+// P = inverse of the diagonal block, by unpivoted Gauss-Jordan in LDS (one workgroup).
+__global__ __launch_bounds__(256) void k_gjb_diag(const double* __restrict__ A, int n, int k0, int b,
+                                                  double* __restrict__ P) {
+    __shared__ double M[kGJB][kGJB + 1];
+    __shared__ double pivrow[kGJB];
+    __shared__ double pivcol[kGJB];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < b * b; q += blockDim.x) M[q / b][q % b] = A[(size_t)(k0 + q / b) * n + k0 + q % b];
+    __syncthreads();
+    for (int p = 0; p < b; ++p) {
+        const double inv = 1.0 / M[p][p];
+        if (tid < b) {
+            pivrow[tid] = tid == p ? inv : M[p][tid] * inv;
+            pivcol[tid] = M[tid][p];
+        }
+        __syncthreads();
+        for (int q = tid; q < b * b; q += blockDim.x) {
+            const int i = q / b, j = q % b;
+            if (i == p) M[i][j] = pivrow[j];
+            else if (j == p) M[i][j] = -pivcol[i] * inv;
+            else M[i][j] -= pivcol[i] * pivrow[j];
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < b * b; q += blockDim.x) P[q] = M[q / b][q % b];
 }
 
-__global__ void k_gj_row(double* A, const double* col, int n, int k) {
+// R[t][j] = sum_s P[t][s] A[k0 + s][j], all columns j (R is b x n).
+__global__ __launch_bounds__(256) void k_gjb_row(const double* __restrict__ A, int n, int k0, int b,
+                                                 const double* __restrict__ P, double* __restrict__ R) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double piv = col[k];
-    const double v = (j == k) ? 1.0 : A[(size_t)k * n + j];
-    A[(size_t)k * n + j] = v / piv;
+    double a[kGJB];
+    for (int s2 = 0; s2 < b; ++s2) a[s2] = A[(size_t)(k0 + s2) * n + j];
+    for (int t = 0; t < b; ++t) {
+        double acc = 0;
+        for (int s2 = 0; s2 < b; ++s2) acc += P[t * b + s2] * a[s2];
+        R[(size_t)t * n + j] = acc;
+    }
 }
 
-// stage 2: A[i][j] -= col[i] * A[k][j] for i != k; column k of other rows becomes -col[i] * (1/piv).
-__global__ void k_gj_update(double* A, const double* col, int n, int k) {
+// A_ij -= sum_t A[i][k0 + t] R[t][j] for i, j outside K: 64 x 64 tiles, 4 x 4 per lane.
+__global__ __launch_bounds__(256) void k_gjb_update(double* __restrict__ A, int n, int k0, int b,
+                                                    const double* __restrict__ R) {
+    __shared__ double Ls[kGJB][64 + 1];  // Ls[t][row]
+    __shared__ double Rs[kGJB][64 + 1];  // Rs[t][col]
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64, tid = threadIdx.x;
+    for (int q = tid; q < 64 * b; q += blockDim.x) {
+        const int r = q / b, t = q % b, i = i0 + r;
+        Ls[t][r] = i < n ? A[(size_t)i * n + k0 + t] : 0.0;
+    }
+    for (int q = tid; q < 64 * b; q += blockDim.x) {
+        const int t = q / 64, cidx = q % 64, j = j0 + cidx;
+        Rs[t][cidx] = j < n ? R[(size_t)t * n + j] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4] = {};
+    for (int t = 0; t < b; ++t) {
+        double l[4], r[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            l[a] = Ls[t][tr + a];
+            r[a] = Rs[t][tc + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += l[a] * r[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + tr + a;
+        if (i >= n || (i >= k0 && i < k0 + b)) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + tc + c;
+            if (j >= n || (j >= k0 && j < k0 + b)) continue;
+            A[(size_t)i * n + j] -= acc[a][c];
+        }
+    }
+}
+
+// A[i][K] = -A[i][K] P for rows outside K; then row block K = R and A_KK = P.
+__global__ __launch_bounds__(256) void k_gjb_col(double* __restrict__ A, int n, int k0, int b,
+                                                 const double* __restrict__ P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (i >= k0 && i < k0 + b)) return;
+    double a[kGJB];
+    for (int s2 = 0; s2 < b; ++s2) a[s2] = A[(size_t)i * n + k0 + s2];
+    for (int t = 0; t < b; ++t) {
+        double acc = 0;
+        for (int s2 = 0; s2 < b; ++s2) acc += a[s2] * P[s2 * b + t];
+        A[(size_t)i * n + k0 + t] = -acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gjb_store(double* __restrict__ A, int n, int k0, int b,
+                                                   const double* __restrict__ R, const double* __restrict__ P) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= n || i == k) return;
-    const double f = col[i];
-    const double akj = A[(size_t)k * n + j];
-    if (j == k) A[(size_t)i * n + j] = -f * akj;
-    else A[(size_t)i * n + j] -= f * akj;
+    if (j >= n) return;
+    const bool inK = j >= k0 && j < k0 + b;
+    for (int t = 0; t < b; ++t) A[(size_t)(k0 + t) * n + j] = inK ? P[t * b + (j - k0)] : R[(size_t)t * n + j];
 }
 
 // y = A x, one 64-lane wave per row, fixed-order reduction.
@@ -1004,11 +1090,19 @@ hipError_t dense_set_unit(double* e, int j, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t dense_invert(double* A, double* col, int n, hipStream_t s) {
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_savecol, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, col, n, k);
-        hipLaunchKernelGGL(k_gj_row, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, col, n, k);
-        hipLaunchKernelGGL(k_gj_update, dim3(blocks_for(n, 256), n), dim3(256), 0, s, A, col, n, k);
+size_t dense_invert_scratch(int n) { return (size_t)kGJB * n + (size_t)kGJB * kGJB; }
+
+hipError_t dense_invert(double* A, double* scratch, int n, hipStream_t s) {
+    double* R = scratch;                       // [kGJB][n]
+    double* P = scratch + (size_t)kGJB * n;    // [kGJB][kGJB]
+    const unsigned tiles = (unsigned)((n + 63) / 64);
+    for (int k0 = 0; k0 < n; k0 += kGJB) {
+        const int b = std::min(kGJB, n - k0);
+        hipLaunchKernelGGL(k_gjb_diag, dim3(1), dim3(256), 0, s, A, n, k0, b, P);
+        hipLaunchKernelGGL(k_gjb_row, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, P, R);
+        hipLaunchKernelGGL(k_gjb_update, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, b, R);
+        hipLaunchKernelGGL(k_gjb_col, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, P);
+        hipLaunchKernelGGL(k_gjb_store, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, R, P);
     }
     return hipGetLastError();
 }

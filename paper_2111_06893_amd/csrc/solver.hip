@@ -945,7 +945,7 @@ void plan_solver(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
         const size_t nc = S.n_coarse;
         S.off_Ainv[0] = lay.take(8 * nc * nc);
         S.off_Ainv[1] = lay.take(4 * nc * nc);
-        S.off_col = lay.take(8 * nc);
+        S.off_col = lay.take(8 * dense_invert_scratch((int)nc));
     }
     const size_t n = ndof(c->levels[0]);
     S.m = std::max(4, std::min(200, opts->restart));
