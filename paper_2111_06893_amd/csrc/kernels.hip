@@ -61,12 +61,19 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     dst[2 * N2] = t[2];
 }
 
-// Waves per SIMD: eight in FP32 (four workgroups of eight waves per CU); seven
-// in FP64, whose 68 registers do not fit eight without spills (measured no
-// faster at 2000 elements, and the spill traffic goes to HBM).  The FP64 lift
-// factors are stored over u (below), which keeps the LDS at 40.5 KB for N = 7.
+// Waves per SIMD asked of the compiler: eight (four workgroups of eight waves
+// per CU at N = 7), except for the FP64 instantiations that need more than the
+// 64 registers this allows and would spill (N = 2, 5, 6: seven).  FP64 at N = 7
+// fits because the face data are read from LDS where used rather than copied
+// into registers, and its lift factors are stored over u (below), which keeps
+// the LDS at 40.5 KB.
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>(), sizeof(R) == 4 ? 8 : 7) void k_apply(LevelView<R> L, const R* __restrict__ u,
+constexpr int apply_waves() {
+    return (sizeof(R) == 8 && (N == 2 || N == 5 || N == 6)) ? 7 : 8;
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_apply(LevelView<R> L, const R* __restrict__ u,
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
     constexpr int N2 = N * N, N3 = N2 * N;
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(line_threads<N>(), sizeof(R) == 4 ? 8 : 7) void k_a
         // face geometry loaded here rather than held through the earlier phases (register pressure)
         const R det2 = L.geo2[(size_t)col * 5 * N2 + 4 * N2 + fi_j * N + fi_i];
         const R hz = sown[3];
-        const FaceInfo<R> fo = sface[f];
+        const FaceInfo<R>& fo = sface[f];  // read from LDS where used
         const R sigma = f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : fo.sig;
         R n[3], amag;
         face_frame<N>(L, col, f, fi_i, fi_j, n, amag);
