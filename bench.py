@@ -53,6 +53,16 @@ PROFILE_COMMANDS = {
              "python3 bench.py --one-solve",
 }
 FP64_PEAK_TFLOPS = 78.6
+
+# The paper's own wall times of its CPU solver (Sec. 3 and Sec. 4), quoted with their
+# hardware as context: other configurations and machines, not a target.
+PAPER_CPU_TIMINGS = {
+    "hardware": "Intel Haswell E5-2630v3 2.4 GHz, 16-core nodes, 15 cores used per node",
+    "single coating, sub-percent error in U": "30 s on 15 cores",
+    "single coating, fractional error 1e-5": "about 2 min wall (half a core-hour) on 15 cores",
+    "simple configurations": "seconds to minutes on 15 cores",
+    "nine sub-micron crystalline layers": "about 1 hour on 45 cores",
+}
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -370,6 +380,7 @@ def main():
         out["forty_layer_adjoint"] = forty_layer_adjoint(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
+    out["paper_cpu_timings"] = PAPER_CPU_TIMINGS
     print(json.dumps(out), flush=True)
 
 
