@@ -2,7 +2,8 @@
 5,184,000 DoF) on the device, at full size.
 
 * Every entry of A u (FP64 and FP32) against the oracle's operator on the same
-  seeded field (tolerances of the operator parity tests).
+  seeded field (tolerances of the operator parity tests), at p = 5 and at the
+  largest size, p = 6 (8,232,000 DoF).
 * Load vector and per-layer energies of a seeded field against the oracle.
 * The adjoint gradient with respect to all forty coating thicknesses (one
   adjoint solve, forty parameter derivatives): the entries of the first and the
@@ -34,8 +35,13 @@ def oracle(spec):
     return dg.Problem(spec)
 
 
-def test_apply_full_size_matches_oracle(spec, oracle):
-    print("[parity] apply config5 full size", flush=True)
+@pytest.mark.parametrize("p", [5, 6])
+def test_apply_full_size_matches_oracle(spec, oracle, p):
+    # p = 6 is the largest size of this workload: 8,232,000 DoF
+    if p != spec["p"]:
+        spec = W.config5(p=p)
+        oracle = dg.Problem(spec)
+    print(f"[parity] apply config5 full size p={p} dof={W.n_dof(spec)}", flush=True)
     P = dgtn.Problem(spec)
     u = W.random_field(spec, seed=5)
     ref = dg.apply(oracle, u)
