@@ -663,18 +663,15 @@ __global__ __launch_bounds__(256) void k_gjb_diag(const double* __restrict__ A, 
     for (int q = tid; q < b * b; q += blockDim.x) P[q] = M[q / b][q % b];
 }
 
-// R[t][j] = sum_s P[t][s] A[k0 + s][j], all columns j (R is b x n).
+// R[t][j] = sum_s P[t][s] A[k0 + s][j], all columns j (R is b x n); one lane per (t, j).
 __global__ __launch_bounds__(256) void k_gjb_row(const double* __restrict__ A, int n, int k0, int b,
                                                  const double* __restrict__ P, double* __restrict__ R) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    double a[kGJB];
-    for (int s2 = 0; s2 < b; ++s2) a[s2] = A[(size_t)(k0 + s2) * n + j];
-    for (int t = 0; t < b; ++t) {
-        double acc = 0;
-        for (int s2 = 0; s2 < b; ++s2) acc += P[t * b + s2] * a[s2];
-        R[(size_t)t * n + j] = acc;
-    }
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)b * n) return;
+    const int t = (int)(q / n), jj = (int)(q % n);
+    double acc = 0;
+    for (int s2 = 0; s2 < b; ++s2) acc += P[t * b + s2] * A[(size_t)(k0 + s2) * n + jj];
+    R[q] = acc;
 }
 
 // A_ij -= sum_t A[i][k0 + t] R[t][j] for i, j outside K: 64 x 64 tiles, 4 x 4 per lane.
@@ -719,26 +716,33 @@ __global__ __launch_bounds__(256) void k_gjb_update(double* __restrict__ A, int 
     }
 }
 
-// A[i][K] = -A[i][K] P for rows outside K; then row block K = R and A_KK = P.
-__global__ __launch_bounds__(256) void k_gjb_col(double* __restrict__ A, int n, int k0, int b,
-                                                 const double* __restrict__ P) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || (i >= k0 && i < k0 + b)) return;
-    double a[kGJB];
-    for (int s2 = 0; s2 < b; ++s2) a[s2] = A[(size_t)i * n + k0 + s2];
-    for (int t = 0; t < b; ++t) {
-        double acc = 0;
-        for (int s2 = 0; s2 < b; ++s2) acc += a[s2] * P[s2 * b + t];
-        A[(size_t)i * n + k0 + t] = -acc;
-    }
+// C[i][t] = -sum_s A[i][k0 + s] P[s][t] (the new column block, rows outside K);
+// one lane per (i, t), written to C so that A's column block stays intact until stored.
+__global__ __launch_bounds__(256) void k_gjb_col(const double* __restrict__ A, int n, int k0, int b,
+                                                 const double* __restrict__ P, double* __restrict__ C) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)n * b) return;
+    const int i = (int)(q / b), t = (int)(q % b);
+    if (i >= k0 && i < k0 + b) return;
+    double acc = 0;
+    for (int s2 = 0; s2 < b; ++s2) acc += A[(size_t)i * n + k0 + s2] * P[s2 * b + t];
+    C[q] = -acc;
 }
 
+// Column block K of the other rows = C; row block K = R, with A_KK = P.
 __global__ __launch_bounds__(256) void k_gjb_store(double* __restrict__ A, int n, int k0, int b,
-                                                   const double* __restrict__ R, const double* __restrict__ P) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const bool inK = j >= k0 && j < k0 + b;
-    for (int t = 0; t < b; ++t) A[(size_t)(k0 + t) * n + j] = inK ? P[t * b + (j - k0)] : R[(size_t)t * n + j];
+                                                   const double* __restrict__ R, const double* __restrict__ P,
+                                                   const double* __restrict__ C) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < (size_t)n * b) {  // column block, one lane per (i, t)
+        const int i = (int)(q / b), t = (int)(q % b);
+        if (i < k0 || i >= k0 + b) A[(size_t)i * n + k0 + t] = C[q];
+    } else if (q < (size_t)2 * n * b) {  // row block, one lane per (t, j)
+        const size_t r = q - (size_t)n * b;
+        const int t = (int)(r / n), jj = (int)(r % n);
+        const bool inK = jj >= k0 && jj < k0 + b;
+        A[(size_t)(k0 + t) * n + jj] = inK ? P[t * b + (jj - k0)] : R[r];
+    }
 }
 
 // y = A x, one 64-lane wave per row, fixed-order reduction.
@@ -1090,19 +1094,21 @@ hipError_t dense_set_unit(double* e, int j, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t dense_invert_scratch(int n) { return (size_t)kGJB * n + (size_t)kGJB * kGJB; }
+size_t dense_invert_scratch(int n) { return 2 * (size_t)kGJB * n + (size_t)kGJB * kGJB; }
 
 hipError_t dense_invert(double* A, double* scratch, int n, hipStream_t s) {
-    double* R = scratch;                       // [kGJB][n]
-    double* P = scratch + (size_t)kGJB * n;    // [kGJB][kGJB]
+    double* R = scratch;                           // [kGJB][n]
+    double* C = scratch + (size_t)kGJB * n;        // [n][kGJB]
+    double* P = scratch + 2 * (size_t)kGJB * n;    // [kGJB][kGJB]
     const unsigned tiles = (unsigned)((n + 63) / 64);
     for (int k0 = 0; k0 < n; k0 += kGJB) {
         const int b = std::min(kGJB, n - k0);
+        const size_t nb = (size_t)n * b;
         hipLaunchKernelGGL(k_gjb_diag, dim3(1), dim3(256), 0, s, A, n, k0, b, P);
-        hipLaunchKernelGGL(k_gjb_row, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, P, R);
+        hipLaunchKernelGGL(k_gjb_row, dim3(blocks_for(nb, 256)), dim3(256), 0, s, A, n, k0, b, P, R);
         hipLaunchKernelGGL(k_gjb_update, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, b, R);
-        hipLaunchKernelGGL(k_gjb_col, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, P);
-        hipLaunchKernelGGL(k_gjb_store, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, n, k0, b, R, P);
+        hipLaunchKernelGGL(k_gjb_col, dim3(blocks_for(nb, 256)), dim3(256), 0, s, A, n, k0, b, P, C);
+        hipLaunchKernelGGL(k_gjb_store, dim3(blocks_for(2 * nb, 256)), dim3(256), 0, s, A, n, k0, b, R, P, C);
     }
     return hipGetLastError();
 }
