@@ -11,8 +11,14 @@
 //                   children (z unchanged).
 //  * k_prolong_z / k_restrict_z   transfers between pairs of z-elements and
 //                   their merged (fiducial-layer) element.
-//  * dense coarse solve: Gauss-Jordan inversion steps and a matrix-vector product.
-//  * vector algebra for FGMRES: fused multi-dot, multi-axpy, casts.
+//  * k_ovl_fwd / k_col_gemm_mfma / k_ovl_bwd / k_ovl_sum   the overlapping
+//                   column-Schwarz smoother: patch gather and x/y transforms, the
+//                   shared z-eigenbasis products on the matrix cores with the
+//                   eigenvalue division, back transforms and the weighted sum.
+//  * dense coarse solve: blocked Gauss-Jordan inversion (k_gjb_*) and a
+//                   matrix-vector product.
+//  * vector algebra for flexible CG and FGMRES: fused dots, CG updates,
+//                   multi-dot, multi-axpy, casts.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
