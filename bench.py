@@ -122,17 +122,20 @@ def time_launches(fn, n, stream):
 def cpu_baseline(spec, budget_s=15.0):
     """The oracle's operator application timed on the host on a bounded sample
     of the same workload (whole applications of A u)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import dg
     O = dg.Problem(spec)
     u = W.random_field(spec, seed=0)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        dg.apply(O, u)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = (time.perf_counter() - t0) / n
+    with threadpool_limits(limits=1):   # BLAS calls of NumPy on one thread: cores = 1
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            dg.apply(O, u)
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = (time.perf_counter() - t0) / n
     return {"value": W.n_dof(spec) / dt, "unit": "DoF/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} oracle applications of A u on the full {W.n_dof(spec)}-DoF workload "
                       f"(NumPy FP64, single thread), {dt:.2f} s each"}
