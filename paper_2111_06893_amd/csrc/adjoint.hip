@@ -89,6 +89,7 @@ LevelView<Dual> dual_view(const dgtn_ctx* c) {
     v.n_cols = L.n_cols;
     v.n_z = L.n_z;
     v.E = L.E;
+    v.e0 = 0;
     v.geo2 = at<const Dual>(c, A.geo2);
     v.sig_side = at<const Dual>(c, A.sig);
     v.fnrm = at<const Dual>(c, A.fnrm);
@@ -285,20 +286,48 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
         }
         AHIP(hipMemcpyAsync(c->ws + A.hz, hz.data(), sizeof(Dual) * hz.size(), hipMemcpyHostToDevice, s));
         AHIP(hipMemcpyAsync(c->ws + A.mat, mat.data(), sizeof(Dual) * mat.size(), hipMemcpyHostToDevice, s));
+        // Element ranges (in z-layers) that see the parameter.  A thickness changes
+        // the element widths of its layer only: rows of A_theta u are nonzero on the
+        // layer and its z-neighbours (penalty, lift and the neighbours' tractions),
+        // which read the tractions of one layer further; K_w,theta lives on the layer.
+        // A material may sit anywhere: whole level.
+        int rz0 = 0, rz1 = L.n_z, tz0 = 0, tz1 = L.n_z, ez0 = 0, ez1 = L.n_z;
+        if (p.kind == DGTN_PARAM_THICKNESS) {
+            int z0 = L.n_z, z1 = 0;
+            for (int iz = 0; iz < L.n_z; ++iz)
+                if (L.zlayer[iz] == p.index) {
+                    z0 = std::min(z0, iz);
+                    z1 = std::max(z1, iz + 1);
+                }
+            ez0 = z0;
+            ez1 = z1;
+            rz0 = std::max(0, z0 - 1);
+            rz1 = std::min(L.n_z, z1 + 1);
+            tz0 = std::max(0, z0 - 2);
+            tz1 = std::min(L.n_z, z1 + 2);
+        }
+        auto range = [&](int a, int b) {
+            LevelView<Dual> r = v;
+            r.e0 = a * L.n_cols;
+            r.E = (b - a) * L.n_cols;
+            return r;
+        };
         // lambda^T A_theta u
-        AHIP(launch_traction<Dual>(v, ud, at<Dual>(c, A.tau), s));
-        AHIP(launch_apply<Dual>(v, ud, at<const Dual>(c, A.tau), Aud, Dual(yr, 0.0), s));
-        hipLaunchKernelGGL(k_dot_deriv, dim3(A.nblk), dim3(kDotThreads), 0, s, lam, Aud, n, at<double>(c, A.partial),
-                           A.nblk);
+        AHIP(launch_traction<Dual>(range(tz0, tz1), ud, at<Dual>(c, A.tau), s));
+        AHIP(launch_apply<Dual>(range(rz0, rz1), ud, at<const Dual>(c, A.tau), Aud, Dual(yr, 0.0), s));
+        const size_t per_layer = n / L.n_z, r_off = (size_t)rz0 * per_layer;
+        hipLaunchKernelGGL(k_dot_deriv, dim3(A.nblk), dim3(kDotThreads), 0, s, lam + r_off, Aud + r_off,
+                           (size_t)(rz1 - rz0) * per_layer, at<double>(c, A.partial), A.nblk);
         AHIP(hipGetLastError());
         // 1/2 u^T K_w,theta u, per element
-        AHIP(launch_energy<Dual>(v, u, at<Dual>(c, A.Ue), s));
+        AHIP(launch_energy<Dual>(range(ez0, ez1), u, at<Dual>(c, A.Ue), s));
+        const int eb = ez0 * L.n_cols, ne = (ez1 - ez0) * L.n_cols;
         AHIP(hipMemcpyAsync(part.data(), at<double>(c, A.partial), 8 * part.size(), hipMemcpyDeviceToHost, s));
-        AHIP(hipMemcpyAsync(Ue.data(), at<Dual>(c, A.Ue), sizeof(Dual) * Ue.size(), hipMemcpyDeviceToHost, s));
+        AHIP(hipMemcpyAsync(Ue.data() + eb, at<Dual>(c, A.Ue) + eb, sizeof(Dual) * ne, hipMemcpyDeviceToHost, s));
         AHIP(hipStreamSynchronize(s));
         double lAu = 0, dU = 0;
         for (double x : part) lAu += x;
-        for (int e = 0; e < L.E; ++e) dU += wz[e / L.n_cols] * Ue[e].d;
+        for (int e = eb; e < eb + ne; ++e) dU += wz[e / L.n_cols] * Ue[e].d;
         dJ[ip] = dU * yr - lAu;
         if (!std::isfinite(dJ[ip])) { set_error("non-finite gradient"); return DGTN_ENAN; }
     }

@@ -31,6 +31,7 @@ LevelView<R> view_of(const dgtn_ctx* c, const Level& L) {
     v.n_cols = L.n_cols;
     v.n_z = L.n_z;
     v.E = L.E;
+    v.e0 = 0;
     char* b = c->ws;
     v.geo2 = reinterpret_cast<const R*>(b + L.off_geo2[pi]);
     v.sig_side = reinterpret_cast<const R*>(b + L.off_sig[pi]);

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy(LevelView<R> L, con
     __shared__ R su[3 * N3];
     __shared__ R sD[N2];
     __shared__ R red[NT];
-    const int e = blockIdx.x;
+    const int e = L.e0 + blockIdx.x;
     const int tid = threadIdx.x;
     const double* ue = u + (size_t)e * 3 * N3;
     for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = R(ue[q]);

@@ -27,6 +27,9 @@ std::vector<double> lagrange_matrix(const Lgl& from, const std::vector<double>& 
 template <typename R>
 struct LevelView {
     int N, n_cols, n_z, E;
+    // The operator and energy kernels process the E elements e0, e0 + 1, ... (the
+    // whole level with e0 = 0; a range of z-layers for parameter derivatives).
+    int e0;
     const R* geo2;       // [n_cols][5][N*N]: a^xi_x, a^xi_y, a^eta_x, a^eta_y, det2
     const R* sig_side;   // [n_cols][4][N]   penalty sigma on the side faces
     const R* fnrm;       // [n_cols][4][3][N] side faces: outward unit normal n_x, n_y and |grad xi^m|

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     __shared__ R su[3 * N3];
     __shared__ R sG[9 * N3];
     __shared__ R sown[5];
-    const int e = xcd_element(blockIdx.x, L.E);
+    const int e = L.e0 + xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     __shared__ R swi[N];
     __shared__ FaceInfo<R> sface[6];
     __shared__ R sown[5];
-    const int e = xcd_element(blockIdx.x, L.E);
+    const int e = L.e0 + xcd_element(blockIdx.x, L.E);
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
