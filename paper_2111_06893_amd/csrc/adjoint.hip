@@ -286,19 +286,23 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
         }
         AHIP(hipMemcpyAsync(c->ws + A.hz, hz.data(), sizeof(Dual) * hz.size(), hipMemcpyHostToDevice, s));
         AHIP(hipMemcpyAsync(c->ws + A.mat, mat.data(), sizeof(Dual) * mat.size(), hipMemcpyHostToDevice, s));
-        // Element ranges (in z-layers) that see the parameter.  A thickness changes
-        // the element widths of its layer only: rows of A_theta u are nonzero on the
-        // layer and its z-neighbours (penalty, lift and the neighbours' tractions),
-        // which read the tractions of one layer further; K_w,theta lives on the layer.
-        // A material may sit anywhere: whole level.
+        // Element ranges (in z-layers) that see the parameter: the z-elements of the
+        // layer (thickness) or of every layer made of the material, from the first to
+        // the last.  K_w,theta lives on them; rows of A_theta u are nonzero on them
+        // and their z-neighbours (penalty, lift, averaged moduli and the neighbours'
+        // tractions), which read the tractions of one layer further.
         int rz0 = 0, rz1 = L.n_z, tz0 = 0, tz1 = L.n_z, ez0 = 0, ez1 = L.n_z;
-        if (p.kind == DGTN_PARAM_THICKNESS) {
+        {
             int z0 = L.n_z, z1 = 0;
             for (int iz = 0; iz < L.n_z; ++iz)
-                if (L.zlayer[iz] == p.index) {
+                if (p.kind == DGTN_PARAM_THICKNESS ? L.zlayer[iz] == p.index : L.zmat[iz] == p.index) {
                     z0 = std::min(z0, iz);
                     z1 = std::max(z1, iz + 1);
                 }
+            if (z1 <= z0) {  // a material no layer uses: no derivative
+                dJ[ip] = 0.0;
+                continue;
+            }
             ez0 = z0;
             ez1 = z1;
             rz0 = std::max(0, z0 - 1);
