@@ -77,3 +77,22 @@ def test_workspace_size_is_reported():
     n = P.workspace_bytes()
     # at least the two face-traction buffers (FP64 + FP32)
     assert n > 40 * 6 * 3 * 36 * 12
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no fallback: without the built library every entry point raises
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libdgtn.so")
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="is not built"):
+        _lib.load()
+    with pytest.raises(RuntimeError):
+        dgtn.Problem(W.config1())
+
+
+def test_device_calls_need_a_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is visible")
+    P = dgtn.Problem(W.config1())
+    with pytest.raises(dgtn.DgtnError, match="no HIP device"):
+        P.bind()
