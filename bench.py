@@ -366,6 +366,11 @@ def main():
         "roofline_f32": {"bound": "hbm", "kernel": "k_apply<7,float>",
                          "achieved": apply_bytes(spec, 4) / k_apply32 / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": apply_bytes(spec, 4) / k_apply32 / 1e9 / HBM_PEAK_GBS},
+        "roofline_traction": {"bound": "hbm", "kernel": "k_traction<7,double>",
+                              "achieved": traction_bytes(spec, 8) / k_trac64 / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s",
+                              "frac": traction_bytes(spec, 8) / k_trac64 / 1e9 / HBM_PEAK_GBS},
+        "apply_pair_hbm_frac": (by64 + traction_bytes(spec, 8)) / a64 / 1e9 / HBM_PEAK_GBS,
         "flop_frac_f64": fl / a64 / 1e12 / FP64_PEAK_TFLOPS,
         "flop_frac_f32": fl / a32 / 1e12 / FP32_PEAK_TFLOPS,
     }
