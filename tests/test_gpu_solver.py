@@ -277,3 +277,22 @@ def test_fiducial_layer_coarsening():
     Mv, Mw = P.precondition(v, o8), P.precondition(w, o8)
     a, b = float(torch.sum(w * Mv)), float(torch.sum(v * Mw))
     assert abs(a - b) < 1e-12 * float(torch.linalg.norm(v) * torch.linalg.norm(Mw))
+
+
+def test_solve_at_the_maximum_degree():
+    """p = 7 (N = 8, the largest degree the kernels take) on the five-block
+    cylinder: the FP64- and FP32-preconditioned solves agree on U, and the
+    solution solves the oracle's discrete system (relative residual of the
+    oracle's operator below 1e-9)."""
+    from oracle import dg
+    spec = W.config1()
+    spec["p"] = 7
+    print("[solve] config1 at p = 7", flush=True)
+    P = dgtn.Problem(spec)
+    u64, s64 = P.solve(opts=dgtn.default_opts(64, rtol=1e-10, max_iter=4000))
+    u32, s32 = P.solve(opts=dgtn.default_opts(32, rtol=1e-10, max_iter=4000))
+    np.testing.assert_allclose(P.energy(u32), P.energy(u64), rtol=1e-9)
+    O = dg.Problem(spec)
+    b = dg.rhs(O)
+    r = b - dg.apply(O, u64.cpu().numpy())
+    assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(b)
