@@ -296,3 +296,25 @@ def test_solve_at_the_maximum_degree():
     b = dg.rhs(O)
     r = b - dg.apply(O, u64.cpu().numpy())
     assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(b)
+
+
+def test_thin_coating_solve_satisfies_the_oracle_system():
+    """The benchmark's workload at full size (2,058,000 DoF): the FP32-
+    preconditioned solve at the benchmark's stopping tolerance and a tight FP64
+    solve, checked with the oracle's operator (relative residuals) and against
+    each other on U (1e-8, the mixed-precision target)."""
+    from oracle import dg
+    spec = W.config2()
+    print("[solve] thin-coating cylinder, full size", flush=True)
+    P = dgtn.Problem(spec)
+    u64, _ = P.solve(opts=dgtn.default_opts(64, rtol=1e-9, max_iter=4000))
+    u32, _ = P.solve(opts=dgtn.default_opts(32, rtol=1e-7, max_iter=4000))
+    U64, U32 = P.energy(u64), P.energy(u32)
+    assert abs(U32.sum() / U64.sum() - 1) < 1e-8
+    O = dg.Problem(spec)
+    b = dg.rhs(O)
+    bn = np.linalg.norm(b)
+    r64 = np.linalg.norm(b - dg.apply(O, u64.cpu().numpy())) / bn
+    r32 = np.linalg.norm(b - dg.apply(O, u32.cpu().numpy())) / bn
+    print(f"oracle residuals: FP64-preconditioned {r64:.2e}, FP32-preconditioned {r32:.2e}", flush=True)
+    assert r64 < 2e-9 and r32 < 2e-7
