@@ -94,3 +94,15 @@ def test_forty_thickness_gradient(spec):
         # about 3e-8) and the adjoint gradient's error is first order in the solution
         # errors, unlike the energies: 1e-4 relative (observed 1.4e-5 on layer 0)
         assert abs(g[k] - fd) < 1e-4 * abs(fd)
+
+
+def test_solve_satisfies_the_oracle_system(spec, oracle):
+    """The FP32-preconditioned solve at its stopping tolerance (5e-8, just above
+    this workload's FP64 residual floor) solves the oracle's discrete system."""
+    print("[solve] config5 against the oracle's operator", flush=True)
+    P = dgtn.Problem(spec)
+    u, _ = P.solve(opts=dgtn.default_opts(32, rtol=5e-8, max_iter=2000), raise_on_noconv=False)
+    b = dg.rhs(oracle)
+    r = np.linalg.norm(b - dg.apply(oracle, u.cpu().numpy())) / np.linalg.norm(b)
+    print(f"oracle residual {r:.2e}", flush=True)
+    assert r < 1e-7
