@@ -9,6 +9,7 @@ namespace dgtn {
 
 template <typename R>
 hipError_t mg_smooth(int N, int E, const R* fdm, const R* b, const R* Ax, R* x, R omega, hipStream_t s);
+// V [2][3][n][n]: the z-eigenvectors of each component (row = z node), then their transposes
 template <typename R>
 hipError_t mg_col_smooth(int N, int n_cols, int n_z, const R* S, const R* lam, const R* rat, const R* V,
                          const R* lz, const R* b, const R* Ax, R* x, R omega, R* T, R* Y, hipStream_t s);

@@ -334,13 +334,16 @@ __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, con
 }
 
 // Batched (over the 3 components, blockIdx.z) product along z:
-//   trans = 1:  Y[i][m] = (sum_z V[z][i] T[z][m]) / (lz[i] + rx lx_a + ry ly_b)
-//   trans = 0:  T[z][m] =  sum_i V[z][i] Y[i][m]
-// V [3][n][n] row = z node, column = mode; in/out [3][n][ncol], m = col*N2 + b*N + a,
+//   div = 1:  Y[i][m] = (sum_z V[z][i] T[z][m]) / (lz[i] + rx lx_a + ry ly_b)
+//   div = 0:  T[z][m] =  sum_i V[z][i] Y[i][m]
+// The left factor A [3][n][n] is read as A[k][row] in both: V itself for div = 1,
+// its stored transpose for div = 0.  in/out [3][n][ncol], m = col*N2 + b*N + a,
 // computed on the matrix cores: 16 x 16 x 4 MFMA blocks (FP64 or FP32
 // inputs and accumulation).  A workgroup of four waves owns a 64 x 64 output
 // tile, each wave a 32 x 32 quarter as 2 x 2 blocks; K is staged through LDS in
-// chunks of 32, the next chunk fetched into registers during the products.
+// chunks of 32, the next chunk fetched into registers during the products, and
+// the eigenvalue denominators of the lane's outputs are fetched before the first
+// chunk so that the division does not wait on memory after the last one.
 // Lane l of a block holds A[l % 16][l / 16] and B[l / 16][l % 16];
 // its four results are C[row(l, q)][l % 16], q = 0..3, with row = 4 (l / 16) + q
 // for the FP32 instruction and row = 4 q + l / 16 for the FP64 one (measured).
@@ -359,10 +362,10 @@ template <> struct MfmaAcc<float> {
 };
 
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
-// W: patch width (the eigenvalue division of trans = 1 splits the column index by
-// W and W^2, compile-time constants here); trans = 0 takes W = 0.
-template <typename R, int W, int trans>
-__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ V,
+// W: patch width (the eigenvalue division splits the column index by W and W^2,
+// compile-time constants here); div = 0 takes W = 0.
+template <typename R, int W, int div>
+__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ A,
                                                        const R* __restrict__ in, R* __restrict__ out,
                                                        const R* __restrict__ lz, const R* __restrict__ lam,
                                                        const R* __restrict__ rat) {
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
     const int row0 = blockIdx.y * kGM, col0 = blockIdx.x * kGN;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
-    const R* Vc = V + (size_t)c * n * n;
+    const R* Ac = A + (size_t)c * n * n;
     const R* Bc = in + (size_t)c * n * ncol;
     // the next K chunk is fetched into registers while the current one is multiplied
     R ra[LA], rb[LB];
@@ -382,17 +385,13 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
-            int kk, rr;
-            if constexpr (trans) { kk = q / kGM; rr = q % kGM; }   // V[k][row]: rows contiguous
-            else { rr = q / kGK; kk = q % kGK; }                   // V[row][k]: k contiguous
-            const int kg = k0 + kk, rg = row0 + rr;
-            ra[t] = (kg < n && rg < n) ? (trans ? Vc[(size_t)kg * n + rg] : Vc[(size_t)rg * n + kg]) : R(0);
+            const int kg = k0 + q / kGM, rg = row0 + q % kGM;
+            ra[t] = (kg < n && rg < n) ? Ac[(size_t)kg * n + rg] : R(0);
         }
 #pragma unroll
         for (int t = 0; t < LB; ++t) {
             const int q = tid + 256 * t;
-            const int kk = q / kGN, cc = q % kGN;
-            const int kg = k0 + kk, cg = col0 + cc;
+            const int kg = k0 + q / kGN, cg = col0 + q % kGN;
             rb[t] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
         }
     };
@@ -402,12 +401,31 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
     fetch(0);
+    // denominators of this lane's outputs (indices clamped: outputs past n or
+    // ncol are computed but not stored)
+    R den[2][2][4];
+    if constexpr (div) {
+        constexpr int W2 = W * W;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int cg = min(col0 + wc + 16 * b + lane % 16, ncol - 1);
+            const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
+            const R lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
+                          rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rg = min(row0 + wr + 16 * a + Acc::row(lane, q), n - 1);
+                    den[a][b][q] = lz[(size_t)c * n + rg] + lxy;
+                }
+        }
+    }
     for (int k0 = 0; k0 < n; k0 += kGK) {
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
-            if constexpr (trans) As[q / kGM][q % kGM] = ra[t];
-            else As[q % kGK][q / kGK] = ra[t];
+            As[q / kGM][q % kGM] = ra[t];
         }
 #pragma unroll
         for (int t = 0; t < LB; ++t) {
@@ -437,19 +455,12 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
         for (int b = 0; b < 2; ++b) {
             const int cg = col0 + wc + 16 * b + lane % 16;
             if (cg >= ncol) continue;
-            R lxy = 0;
-            if constexpr (trans) {
-                constexpr int W2 = W * W;
-                const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
-                lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
-                      rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
-            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rg = row0 + wr + 16 * a + Acc::row(lane, q);
                 if (rg >= n) continue;
                 R v = acc[a][b][q];
-                if constexpr (trans) v /= lz[(size_t)c * n + rg] + lxy;
+                if constexpr (div) v /= den[a][b][q];
                 Oc[(size_t)rg * ncol + cg] = v;
             }
         }
@@ -921,6 +932,7 @@ hipError_t dispatch(int N, F&& f) {
 }
 
 // Both z-products of one smoother application: Y = (V^T T) / (lz + lxy), then T = V Y.
+// V [2][3][n][n] holds the eigenvectors and, after them, their transposes.
 template <typename R>
 hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
                          hipStream_t s) {
@@ -948,7 +960,8 @@ hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R
         default: break;
     }
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_col_gemm_mfma<R, 0, 0>), grid, dim3(256), 0, s, n, ncol, V, Y, T, lz, lam, rat);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R, 0, 0>), grid, dim3(256), 0, s, n, ncol, V + (size_t)3 * n * n, Y, T, lz,
+                       lam, rat);
     return hipGetLastError();
 }
 

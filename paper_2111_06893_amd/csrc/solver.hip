@@ -576,7 +576,7 @@ struct ColumnData {
     std::vector<int> pg;      // [n_cols][P*P]     patch gather table (overlap only)
     std::vector<int> ps;      // [n_cols][N*N][4]  patch sum table (overlap only)
     std::vector<double> rat;  // [n_cols][3][2]    horizontal modulus / c44 per component
-    std::vector<double> V;    // [3][n][n]         z-eigenvectors (row = z node, column = mode)
+    std::vector<double> V;    // [2][3][n][n]      z-eigenvectors (row = z node, column = mode), then transposed
     std::vector<double> Lz;   // [3][n]
 };
 
@@ -679,7 +679,7 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
                 }
     }
     // z: one generalized eigenproblem per component, K_z V = M V diag(lz), M = diag(c44 w h / 2)
-    out.V.assign((size_t)3 * n * n, 0.0);
+    out.V.assign((size_t)6 * n * n, 0.0);
     out.Lz.assign((size_t)3 * n, 0.0);
     std::vector<double> ms(n);
     for (int e = 0; e < nz; ++e)
@@ -706,6 +706,11 @@ void build_column(const dgtn_ctx* c, const Level& L, int overlap, ColumnData& ou
     other.join();
     std::copy(out.V.begin(), out.V.begin() + (size_t)n * n, out.V.begin() + (size_t)n * n);
     std::copy(out.Lz.begin(), out.Lz.begin() + n, out.Lz.begin() + n);
+    // the transposes, so that both z-products read their left factor with the row index contiguous
+    double* Vt = out.V.data() + (size_t)3 * n * n;
+    for (int cc = 0; cc < 3; ++cc)
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < n; ++a) Vt[((size_t)cc * n + a) * n + i] = out.V[((size_t)cc * n + i) * n + a];
 }
 
 // ---- level hierarchy -----------------------------------------------------------
