@@ -21,6 +21,7 @@
 //                   multi-dot, multi-axpy, casts.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "mg.h"
@@ -762,17 +763,48 @@ __global__ __launch_bounds__(256) void k_gjb_store(double* __restrict__ A, int n
     }
 }
 
-// y = A x, one 64-lane wave per row, fixed-order reduction.
-template <typename R>
-__global__ void k_gemv(const R* __restrict__ A, const R* __restrict__ x, R* __restrict__ y, int n) {
+// y = A x, one 64-lane wave per row, fixed-order reduction.  VEC: 16-byte loads
+// (the host takes this form only when n is a multiple of 16 / sizeof(R) and A
+// and x are 16-byte aligned, so that every row starts on a 16-byte boundary),
+// four loads per lane in flight on four accumulators.
+template <typename R, bool VEC>
+__global__ __launch_bounds__(256) void k_gemv(const R* __restrict__ A, const R* __restrict__ x, R* __restrict__ y,
+                                              int n) {
     const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     if (row >= n) return;
-    R acc = 0;
     const R* a = A + (size_t)row * n;
-    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) y[row] = acc;
+    R acc[4] = {0, 0, 0, 0};
+    if constexpr (VEC) {
+        constexpr int V = 16 / sizeof(R);
+        typedef R vec_t __attribute__((ext_vector_type(V)));
+        const vec_t* av = reinterpret_cast<const vec_t*>(a);
+        const vec_t* xv = reinterpret_cast<const vec_t*>(x);
+        const int nv = n / V;
+        int j = lane;
+        for (; j + 192 < nv; j += 256) {
+            vec_t p[4], q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                p[u] = av[j + 64 * u];
+                q[u] = xv[j + 64 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < V; ++t) acc[u] += p[u][t] * q[u][t];
+        }
+        for (; j < nv; j += 64) {
+            const vec_t p = av[j], q = xv[j];
+#pragma unroll
+            for (int t = 0; t < V; ++t) acc[0] += p[t] * q[t];
+        }
+    } else {
+        for (int j = lane; j < n; j += 64) acc[0] += a[j] * x[j];
+    }
+    R r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+    if (lane == 0) y[row] = r;
 }
 
 template <typename R>
@@ -894,24 +926,36 @@ struct DotPairs {
     int np;
 };
 
-// partial[v][blk] = x_v . y_v over the block's slice (fixed order).
+// partial[v][blk] = x_v . y_v over the block's slice (fixed order): the NP
+// pairs are read in one pass, then reduced across each wave by shuffles and
+// across the block's waves in wave order.
+template <int NP>
 __global__ __launch_bounds__(kDotThreads) void k_dotpairs(DotPairs d, size_t n, double* __restrict__ partial,
                                                           int nblk) {
-    __shared__ double red[kDotThreads];
-    const int tid = threadIdx.x;
+    constexpr int NW = kDotThreads / 64;
+    __shared__ double red[NP][NW];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const size_t chunk = (n + nblk - 1) / nblk;
     const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
-    for (int v = 0; v < d.np; ++v) {
-        double acc = 0;
-        for (size_t q = lo + tid; q < hi; q += kDotThreads) acc += d.x[v][q] * d.y[v][q];
-        red[tid] = acc;
-        __syncthreads();
-        for (int s = kDotThreads / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        if (tid == 0) partial[(size_t)v * nblk + blockIdx.x] = red[0];
-        __syncthreads();
+    double acc[NP];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) acc[v] = 0;
+#pragma unroll 4
+    for (size_t q = lo + tid; q < hi; q += kDotThreads)
+#pragma unroll
+        for (int v = 0; v < NP; ++v) acc[v] += d.x[v][q] * d.y[v][q];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+        double r = acc[v];
+        for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+        if (lane == 0) red[v][wave] = r;
+    }
+    __syncthreads();
+    if (tid < NP) {
+        double r = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) r += red[tid][w];
+        partial[(size_t)tid * nblk + blockIdx.x] = r;
     }
 }
 
@@ -1134,7 +1178,12 @@ hipError_t dense_invert(double* A, double* scratch, int n, hipStream_t s) {
 
 template <typename R>
 hipError_t dense_gemv(const R* A, const R* x, R* y, int n, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemv<R>), dim3(blocks_for((size_t)n * 64, 256)), dim3(256), 0, s, A, x, y, n);
+    const bool vec = n % (16 / (int)sizeof(R)) == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(x) % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_gemv<R, true>), dim3(blocks_for((size_t)n * 64, 256)), dim3(256), 0, s, A, x, y, n);
+    else
+        hipLaunchKernelGGL((k_gemv<R, false>), dim3(blocks_for((size_t)n * 64, 256)), dim3(256), 0, s, A, x, y, n);
     return hipGetLastError();
 }
 
@@ -1199,7 +1248,13 @@ hipError_t vec_dotpairs(int np, const double* const* x, const double* const* y, 
         d.x[v] = x[v];
         d.y[v] = y[v];
     }
-    hipLaunchKernelGGL(k_dotpairs, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk);
+    switch (np) {
+        case 1: hipLaunchKernelGGL(k_dotpairs<1>, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk); break;
+        case 2: hipLaunchKernelGGL(k_dotpairs<2>, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk); break;
+        case 3: hipLaunchKernelGGL(k_dotpairs<3>, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk); break;
+        case 4: hipLaunchKernelGGL(k_dotpairs<4>, dim3(nblk), dim3(kDotThreads), 0, s, d, n, partial, nblk); break;
+        default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_reduce_partials, dim3(np), dim3(kDotThreads), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
