@@ -219,12 +219,16 @@ __global__ __launch_bounds__(nthreads<N>()) void k_col_bwd(int n_cols, int nzN, 
 // src_col * N^2 + j * N + i, or -1 where the patch has no node (outside the
 // domain, or a corner at a vertex that is not shared by four columns).
 
+// Threads of a patch workgroup: a compile-time stride, so that the loops over a
+// patch's values unroll and their loads are issued together.
+constexpr int kOvlThreads = 256;
+
 // Gather of r = b - Ax (or b) onto the patches and forward x/y transform:
 // T[c][iz*N + k][col*P2 + b'*P + a'] = sum_{a,b} Sx[a][a'] Sy[b][b'] r_patch[c][k][b][a].
 // P = N + 2 overlap is a template parameter: every index split below is by a
 // compile-time constant and the transform loops unroll.
 template <int N, int P, typename R>
-__global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, const int* __restrict__ pg,
+__global__ __launch_bounds__(kOvlThreads) void k_ovl_fwd(int n_cols, int nzN, const int* __restrict__ pg,
                                                  const R* __restrict__ wsq, const R* __restrict__ S,
                                                  const R* __restrict__ b, const R* __restrict__ Ax,
                                                  R* __restrict__ T) {
@@ -236,19 +240,41 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, const int*
     R* sS = st + NP;
     const int e = blockIdx.x, tid = threadIdx.x;
     const int col = e % n_cols, iz = e / n_cols;
-    for (int q = tid; q < 2 * P2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * P2 + q];
-    for (int q = tid; q < NP; q += blockDim.x) {
-        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2;
-        const int src = pg[(size_t)col * P2 + ab];
-        R v = 0;
-        if (src >= 0) {
-            const size_t o = ((size_t)(iz * n_cols + src / N2) * 3 + c) * N3 + k * N2 + src % N2;
-            v = (Ax ? b[o] - Ax[o] : b[o]) * wsq[src];
+#pragma unroll
+    for (int q = tid; q < 2 * P2; q += kOvlThreads) sS[q] = S[(size_t)col * 2 * P2 + q];
+    // the gather in three phases (table entries, then every value load, then the
+    // selects), so that a thread's loads are in flight together; items past NP
+    // take the last item's indices and holes (src < 0) node 0's, and neither is stored
+    auto gather = [&](auto has_ax) {
+        constexpr bool HA = decltype(has_ax)::value;
+        constexpr int IT = (NP + kOvlThreads - 1) / kOvlThreads;
+        int src[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int q = min(tid + t * kOvlThreads, NP - 1);
+            src[t] = pg[(size_t)col * P2 + (q % (N * P2)) % P2];
         }
-        sr[q] = v;
-    }
+        R vb[IT], va[IT], vw[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int q = min(tid + t * kOvlThreads, NP - 1);
+            const int c = q / (N * P2), k = (q % (N * P2)) / P2, sc = max(src[t], 0);
+            const size_t o = ((size_t)(iz * n_cols + sc / N2) * 3 + c) * N3 + k * N2 + sc % N2;
+            vb[t] = b[o];
+            if constexpr (HA) va[t] = Ax[o];
+            vw[t] = wsq[sc];
+        }
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int q = tid + t * kOvlThreads;
+            if (q < NP) sr[q] = src[t] >= 0 ? (HA ? vb[t] - va[t] : vb[t]) * vw[t] : R(0);
+        }
+    };
+    if (Ax) gather(std::true_type{});
+    else gather(std::false_type{});
     __syncthreads();
-    for (int q = tid; q < NP; q += blockDim.x) {  // x: st[c][k][b][a'] = sum_a Sx[a][a'] sr[c][k][b][a]
+#pragma unroll
+    for (int q = tid; q < NP; q += kOvlThreads) {  // x: st[c][k][b][a'] = sum_a Sx[a][a'] sr[c][k][b][a]
         const int row = q / P, a2 = q % P;
         R acc = 0;
 #pragma unroll
@@ -257,7 +283,8 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, const int*
     }
     __syncthreads();
     const size_t ld = (size_t)n_cols * P2;
-    for (int q = tid; q < NP; q += blockDim.x) {  // y
+#pragma unroll
+    for (int q = tid; q < NP; q += kOvlThreads) {  // y
         const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2, b2 = ab / P, a2 = ab % P;
         const R* sy = sS + P2;
         const R* src = st + (size_t)(c * N + k) * P2;
@@ -270,7 +297,7 @@ __global__ __launch_bounds__(256) void k_ovl_fwd(int n_cols, int nzN, const int*
 
 // Backward x/y transform in place: T[..][col*P2 + b*P + a] = sum Sx[a][a'] Sy[b][b'] T[..][b'*P + a'].
 template <int N, int P, typename R>
-__global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, const R* __restrict__ S,
+__global__ __launch_bounds__(kOvlThreads) void k_ovl_bwd(int n_cols, int nzN, const R* __restrict__ S,
                                                  R* __restrict__ T) {
     extern __shared__ char smem[];
     constexpr int P2 = P * P, NP = 3 * N * P2;
@@ -280,13 +307,26 @@ __global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, const R* _
     const int e = blockIdx.x, tid = threadIdx.x;
     const int col = e % n_cols, iz = e / n_cols;
     const size_t ld = (size_t)n_cols * P2;
-    for (int q = tid; q < 2 * P2; q += blockDim.x) sS[q] = S[(size_t)col * 2 * P2 + q];
-    for (int q = tid; q < NP; q += blockDim.x) {
-        const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2;
-        sr[q] = T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab];
+#pragma unroll
+    for (int q = tid; q < 2 * P2; q += kOvlThreads) sS[q] = S[(size_t)col * 2 * P2 + q];
+    {  // every load of the thread first (items past NP re-read the last one), then the stores
+        constexpr int IT = (NP + kOvlThreads - 1) / kOvlThreads;
+        R v[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int q = min(tid + t * kOvlThreads, NP - 1);
+            const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2;
+            v[t] = T[((size_t)c * nzN + iz * N + k) * ld + (size_t)col * P2 + ab];
+        }
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int q = tid + t * kOvlThreads;
+            if (q < NP) sr[q] = v[t];
+        }
     }
     __syncthreads();
-    for (int q = tid; q < NP; q += blockDim.x) {  // y: st[c][k][b][a'] = sum_b' Sy[b][b'] sr[c][k][b'][a']
+#pragma unroll
+    for (int q = tid; q < NP; q += kOvlThreads) {  // y: st[c][k][b][a'] = sum_b' Sy[b][b'] sr[c][k][b'][a']
         const int row = q / P2, ab = q % P2, bb = ab / P, a2 = ab % P;
         const R* sy = sS + P2;
         const R* src = sr + (size_t)row * P2;
@@ -296,7 +336,8 @@ __global__ __launch_bounds__(256) void k_ovl_bwd(int n_cols, int nzN, const R* _
         st[q] = acc;
     }
     __syncthreads();
-    for (int q = tid; q < NP; q += blockDim.x) {  // x
+#pragma unroll
+    for (int q = tid; q < NP; q += kOvlThreads) {  // x
         const int c = q / (N * P2), rem = q % (N * P2), k = rem / P2, ab = rem % P2, aa = ab % P;
         const R* src = st + (size_t)q - aa;
         R acc = 0;
@@ -324,14 +365,21 @@ __global__ __launch_bounds__(256) void k_ovl_sum(int n_cols, int n_z, int P, con
     const int col = (int)(e % n_cols), iz = (int)(e / n_cols);
     const int P2 = P * P, nzN = n_z * N;
     const R* row = T + ((size_t)c * nzN + iz * N + k) * (size_t)n_cols * P2;
-    const int* tab = ps + ((size_t)col * N2 + node) * 4;
+    // the node's four slots in one 16-byte load (the workspace and every block in
+    // it are 256-byte aligned), then the four values loaded together (an empty
+    // slot re-reads position 0 and is not added)
+    const int4 tab = *reinterpret_cast<const int4*>(ps + ((size_t)col * N2 + node) * 4);
+    const int ts[4] = {tab.x, tab.y, tab.z, tab.w};
+    R v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = row[max(ts[q], 0)];
+    const R w = wsq[(size_t)col * N2 + node];
+    const R x0 = accumulate ? x[o] : R(0);
     R acc = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int t = tab[q];
-        if (t >= 0) acc += row[t];
-    }
-    x[o] = (accumulate ? x[o] : R(0)) + omega * wsq[(size_t)col * N2 + node] * acc;
+    for (int q = 0; q < 4; ++q)
+        if (ts[q] >= 0) acc += v[q];
+    x[o] = x0 + omega * w * acc;
 }
 
 // Batched (over the 3 components, blockIdx.z) product along z:
@@ -1075,7 +1123,7 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
         constexpr int NN = decltype(nn)::value;
         return dispatch_patch<NN>(P, [&](auto pp) {
             constexpr int PP = decltype(pp)::value;
-            hipLaunchKernelGGL((k_ovl_fwd<NN, PP, R>), dim3(E), dim3(256), shm, s, n_cols, n, pg, wsq, S, b, Ax, T);
+            hipLaunchKernelGGL((k_ovl_fwd<NN, PP, R>), dim3(E), dim3(kOvlThreads), shm, s, n_cols, n, pg, wsq, S, b, Ax, T);
             return hipGetLastError();
         });
     });
@@ -1085,7 +1133,7 @@ hipError_t mg_ovl_smooth(int N, int n_cols, int n_z, int P, const int* pg, const
         constexpr int NN = decltype(nn)::value;
         const hipError_t e = dispatch_patch<NN>(P, [&](auto pp) {
             constexpr int PP = decltype(pp)::value;
-            hipLaunchKernelGGL((k_ovl_bwd<NN, PP, R>), dim3(E), dim3(256), shm, s, n_cols, n, S, T);
+            hipLaunchKernelGGL((k_ovl_bwd<NN, PP, R>), dim3(E), dim3(kOvlThreads), shm, s, n_cols, n, S, T);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
