@@ -192,6 +192,21 @@ __device__ __forceinline__ NodeGeo<R> node_geo(const LevelView<R>& L, int col, i
     return r;
 }
 
+// Copies CNT consecutive values into LDS with a workgroup of NT threads: every
+// load of a thread is issued before its first store, so that they are in flight
+// together.  Items past CNT re-read the last value and store it again in its own
+// slot (the same value from every such thread): no branch, so the compiler cannot
+// sink a load into one behind the stores.
+template <int CNT, int NT, typename R>
+__device__ __forceinline__ void stage_to_lds(R* dst, const R* __restrict__ src, int tid) {
+    constexpr int IT = (CNT + NT - 1) / NT;
+    R v[IT];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) v[t] = src[min(tid + t * NT, CNT - 1)];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) dst[min(tid + t * NT, CNT - 1)] = v[t];
+}
+
 // Workgroups are dispatched round-robin over the eight XCDs; map them so that
 // each XCD processes one contiguous range of elements, whose face neighbours
 // (the next column and the next z-layer) then mostly sit in the same L2.

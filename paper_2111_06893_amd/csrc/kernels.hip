@@ -31,8 +31,11 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
-    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    if (tid == 0) {
+    // waves 1.. stage u while wave 0 reads the element's material (two dependent
+    // table reads), so that the two latencies overlap instead of adding up
+    if (tid >= 64) {
+        stage_to_lds<3 * N3, line_threads<N>() - 64>(su, ue, tid - 64);
+    } else if (tid == 0) {
         const int m = L.zmat[iz];
         sown[0] = L.mat[3 * m];
         sown[1] = L.mat[3 * m + 1];
@@ -93,12 +96,18 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
-    for (int q = tid; q < 3 * N3; q += blockDim.x) su[q] = ue[q];
-    for (int q = tid; q < N; q += blockDim.x) {
-        sw[q] = L.w[q];
-        swi[q] = R(1) / L.w[q];
+    // waves 1.. stage u and the weights (threads past N store the last weight
+    // again) while wave 0 resolves the face records, whose table reads depend on
+    // one another: the two latencies overlap instead of adding up
+    if (tid >= 64) {
+        const int t = tid - 64;
+        const R wq = L.w[min(t, N - 1)];
+        stage_to_lds<3 * N3, line_threads<N>() - 64>(su, ue, t);
+        sw[min(t, N - 1)] = wq;
+        swi[min(t, N - 1)] = R(1) / wq;
+    } else {
+        load_faces<N>(L, col, iz, tid, sface, sown);
     }
-    load_faces<N>(L, col, iz, tid, sface, sown);
     // node role
     const bool nact = tid < N3;
     const int i = tid % N, j = (tid / N) % N, k = tid / N2;
