@@ -1,9 +1,10 @@
 """GPU checks of the preconditioner and of the Krylov solve, through the C ABI.
 
 * One V-cycle of the library equals a NumPy V-cycle assembled from the oracle's
-  operators on the same levels (fine p = 3 and coarse p = 1 with the fine
-  level's penalty, dense coarse inverse), the library's own Schwarz subdomain
-  data and LGL interpolation: FP64 to 1e-10, FP32 to 1e-4.
+  operators on the same levels (fine p = 3 and coarse p = 1, or fine p = 5 and
+  coarse p = 2 with an odd number of coarse unknowns, with the fine level's
+  penalty, dense coarse inverse), the library's own Schwarz subdomain data and
+  LGL interpolation: FP64 to 1e-10, FP32 to 1e-4.
 * The FP64 solve (flexible CG, multigrid with the overlapping column-Schwarz
   smoother) reproduces the oracle's converged layer energies (stored by
   tests/golden/make_golden.py, which calls only the oracle; CG to 1e-13 on the
@@ -60,25 +61,25 @@ def _fdm_apply(P, opts, r):
     return out
 
 
-@pytest.mark.parametrize("nu,omega", [(1, 1.0), (2, 0.7)])
-def test_vcycle_matches_numpy_reference(nu, omega):
-    mats = [W.FUSED_SILICA, W.CRYSTAL_A]
-    spec = W.box(nx=2, ny=2, Lx=1.0, Ly=0.7, p=3, materials=mats,
-                 layers=[{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
-                         {"thickness": 0.6, "n_elem": 2, "ratio": 2.0, "material": 0}])
-    print(f"[solver] vcycle reference nu={nu} omega={omega}", flush=True)
+def _vcycle_check(spec, nu, omega, n_coarse):
+    """One library V-cycle (two levels, dense coarse inverse, non-overlapping
+    smoother) against the same V-cycle from the oracle's operators."""
     P = dgtn.Problem(spec)
     opts = dgtn.default_opts(64, mg_levels=2, smooth_steps=nu, smooth_damping=omega, smoother=0, krylov=0)
-    assert P.level_info(opts, 1)[0] == 2
+    Nf = spec["p"] + 1
+    Nc = P.level_info(opts, 1)[0]
+    assert Nc == max(1, spec["p"] // 2) + 1
     v = W.random_field(spec, seed=21)
     z = P.precondition(_dev(v), opts).cpu().numpy()
     yref = P.y_ref
     Of = dg.Problem(spec)
-    coarse = dict(spec, p=1, penalty=spec["penalty"] * (4 / 2) ** 2)
+    # the finest level's penalty on the coarse level: C Nf^2 = C' Nc^2
+    coarse = dict(spec, p=Nc - 1, penalty=spec["penalty"] * (Nf / Nc) ** 2)
     Oc = dg.Problem(coarse)
     Ac = dg.assemble_dense(Oc) / yref
-    xf, _ = lgl.nodes_weights(4)
-    xc, _ = lgl.nodes_weights(2)
+    assert Ac.shape[0] == n_coarse
+    xf, _ = lgl.nodes_weights(Nf)
+    xc, _ = lgl.nodes_weights(Nc)
     I = lgl.interp_matrix(xc, xf)
 
     def A(x):
@@ -97,6 +98,28 @@ def test_vcycle_matches_numpy_reference(nu, omega):
     opts32 = dgtn.default_opts(32, mg_levels=2, smooth_steps=nu, smooth_damping=omega, smoother=0, krylov=0)
     z32 = P.precondition(_dev(v), opts32).cpu().numpy()
     assert np.abs(z32 - x).max() <= 1e-4 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("nu,omega", [(1, 1.0), (2, 0.7)])
+def test_vcycle_matches_numpy_reference(nu, omega):
+    mats = [W.FUSED_SILICA, W.CRYSTAL_A]
+    spec = W.box(nx=2, ny=2, Lx=1.0, Ly=0.7, p=3, materials=mats,
+                 layers=[{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
+                         {"thickness": 0.6, "n_elem": 2, "ratio": 2.0, "material": 0}])
+    print(f"[solver] vcycle reference nu={nu} omega={omega}", flush=True)
+    # coarse level p = 1: 12 elements x 3 x 8 = 288 unknowns (the dense product's 16-byte path)
+    _vcycle_check(spec, nu, omega, 288)
+
+
+def test_vcycle_odd_coarse_size():
+    # fine p = 5, coarse p = 2 on three elements: 3 x 3 x 27 = 243 unknowns, an odd
+    # count, so the dense coarse product takes its scalar-load path in both precisions
+    mats = [W.FUSED_SILICA, W.CRYSTAL_A]
+    spec = W.box(nx=1, ny=1, Lx=1.0, Ly=0.7, p=5, materials=mats,
+                 layers=[{"thickness": 0.05, "n_elem": 1, "ratio": 1, "material": 1},
+                         {"thickness": 0.6, "n_elem": 2, "ratio": 2.0, "material": 0}])
+    print("[solver] vcycle reference, odd coarse size", flush=True)
+    _vcycle_check(spec, 2, 0.7, 243)
 
 
 def _solve_energy(spec, prec, floor_ok=False, **kw):
