@@ -919,10 +919,12 @@ __global__ __launch_bounds__(kDotThreads) void k_reduce_partials(const double* _
 // Flexible-CG steps with the scalars kept on the device (no host round trip):
 // sc[0] = p.Ap, sc[1] = breakdown flag; cur[0] = r.z of this iteration.
 // u += alpha p, r -= alpha Ap with alpha = cur[0] / sc[0]; a non-positive p.Ap
-// skips the update and raises the flag for the host to act on.
+// skips the update and raises the flag for the host to act on.  r32, if not
+// null, receives the new residual rounded to FP32 (the FP32 preconditioner's
+// input, written here instead of by a separate pass).
 __global__ void k_fcg_update(double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
                              const double* __restrict__ q, const double* __restrict__ cur,
-                             double* __restrict__ sc, size_t n) {
+                             double* __restrict__ sc, float* __restrict__ r32, size_t n) {
     const double pq = sc[0];
     const bool ok = pq > 0;
     const double alpha = ok ? cur[0] / pq : 0.0;
@@ -930,7 +932,9 @@ __global__ void k_fcg_update(double* __restrict__ u, double* __restrict__ r, con
     if (!ok && t == 0) sc[1] = 1.0;
     if (t >= n) return;
     u[t] += alpha * p[t];
-    r[t] -= alpha * q[t];
+    const double rn = r[t] - alpha * q[t];
+    r[t] = rn;
+    if (r32) r32[t] = (float)rn;
 }
 
 // p = z + beta p, beta = (nxt[0] - nxt[1]) / cur[0]  (Polak-Ribiere)
@@ -1004,6 +1008,43 @@ __global__ __launch_bounds__(kDotThreads) void k_dotpairs(DotPairs d, size_t n, 
 #pragma unroll
         for (int w = 0; w < NW; ++w) r += red[tid][w];
         partial[(size_t)tid * nblk + blockIdx.x] = r;
+    }
+}
+
+// The three dot products of a flexible-CG step with an FP32 preconditioner:
+// zn = (double) z32 is written here (the widening pass folded in), and
+// partial[0..2][blk] = r.zn, r.zo, r.r over the block's slice, in the order
+// and with the reductions of k_dotpairs<3>.
+__global__ __launch_bounds__(kDotThreads) void k_dot3_widen(const double* __restrict__ r,
+                                                            const float* __restrict__ z32, double* __restrict__ zn,
+                                                            const double* __restrict__ zo, size_t n,
+                                                            double* __restrict__ partial, int nblk) {
+    constexpr int NW = kDotThreads / 64;
+    __shared__ double red[3][NW];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t lo = (size_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double acc[3] = {0, 0, 0};
+#pragma unroll 4
+    for (size_t q = lo + tid; q < hi; q += kDotThreads) {
+        const double rq = r[q], z = (double)z32[q];
+        zn[q] = z;
+        acc[0] += rq * z;
+        acc[1] += rq * zo[q];
+        acc[2] += rq * rq;
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double x = acc[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) red[v][wave] = x;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double x = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) x += red[tid][w];
+        partial[(size_t)tid * nblk + blockIdx.x] = x;
     }
 }
 
@@ -1261,8 +1302,15 @@ hipError_t vec_multidot(const double* V, size_t ldv, int nv, const double* w, si
 }
 
 hipError_t fcg_update(double* u, double* r, const double* p, const double* q, const double* cur, double* sc,
-                      size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, r, p, q, cur, sc, n);
+                      float* r32, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, r, p, q, cur, sc, r32, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_dot3_widen(const double* r, const float* z32, double* zn, const double* zo, size_t n, double* partial,
+                          int nblk, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot3_widen, dim3(nblk), dim3(kDotThreads), 0, s, r, z32, zn, zo, n, partial, nblk);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(3), dim3(kDotThreads), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
 

@@ -1401,6 +1401,8 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         double* q = w;                     // A p
         double* sc = at<double>(c, S.off_sc);  // [0] p.Ap, [1] breakdown flag, [4 + 4s ..] r.z slots
         const int refresh = 50;
+        // FP32 preconditioner input (level 0), written by the CG update; null otherwise
+        float* const b32 = opts->precond_precision == 32 && !vo.identity ? at<float>(c, S.mg[0].off_b[1]) : nullptr;
         if ((st = S.host_monitor()) != DGTN_OK) return st;
         auto slot = [&](int k) { return sc + 4 + 4 * (k & 1); };
         int par = 0;
@@ -1431,18 +1433,28 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
             if ((st = level_apply<double>(c, 0, pp, q, yr, s)) != DGTN_OK) return st;
             dx[0] = pp; dy[0] = q;
             SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, sc, s));
-            SHIP(fcg_update(u, pr, pp, q, cur, sc, n, s));
+            // FP32 V-cycle: the update writes its input and the dot products widen its
+            // output (the same roundings as precondition's two casts, without their passes)
+            SHIP(fcg_update(u, pr, pp, q, cur, sc, b32, n, s));
             const int it = iters++;
-            if (iters % refresh == 0) {  // residual replacement
+            const bool replace = iters % refresh == 0;
+            if (replace) {  // residual replacement
                 if ((st = level_apply<double>(c, 0, u, pr, yr, s)) != DGTN_OK) return st;
                 SHIP(vec_resid<double>(b, pr, n, s));
                 ++restarts;
             }
-            if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
-            dx[0] = pr; dy[0] = zn;
-            dx[1] = pr; dy[1] = zo;
-            dx[2] = pr; dy[2] = pr;
-            SHIP(vec_dotpairs(3, dx, dy, n, at<double>(c, S.off_partial), S.nblk, nxt, s));
+            if (b32) {
+                if (replace) SHIP(vec_cast<double, float>(pr, b32, n, 1.0, s));
+                if ((st = vcycle_launch(c, 32, vo, s)) != DGTN_OK) return st;
+                SHIP(vec_dot3_widen(pr, at<float>(c, S.mg[0].off_x[1]), zn, zo, n, at<double>(c, S.off_partial),
+                                    S.nblk, nxt, s));
+            } else {
+                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
+                dx[0] = pr; dy[0] = zn;
+                dx[1] = pr; dy[1] = zo;
+                dx[2] = pr; dy[2] = pr;
+                SHIP(vec_dotpairs(3, dx, dy, n, at<double>(c, S.off_partial), S.nblk, nxt, s));
+            }
             SHIP(fcg_direction(pp, zn, cur, nxt, n, s));
             std::swap(zn, zo);
             par ^= 1;
