@@ -369,7 +369,8 @@ def main():
         "roofline_traction": {"bound": "hbm", "kernel": "k_traction<7,double>",
                               "achieved": traction_bytes(spec, 8) / k_trac64 / 1e9, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s",
-                              "frac": traction_bytes(spec, 8) / k_trac64 / 1e9 / HBM_PEAK_GBS},
+                              "frac": traction_bytes(spec, 8) / k_trac64 / 1e9 / HBM_PEAK_GBS,
+                              "traffic": None, "bytes_per_launch": traction_bytes(spec, 8)},
         "apply_pair_hbm_frac": (by64 + traction_bytes(spec, 8)) / a64 / 1e9 / HBM_PEAK_GBS,
         "flop_frac_f64": fl / a64 / 1e12 / FP64_PEAK_TFLOPS,
         "flop_frac_f32": fl / a32 / 1e12 / FP32_PEAK_TFLOPS,
@@ -377,6 +378,9 @@ def main():
     traffic = measured_traffic()
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
+    traffic = measured_traffic("traction")
+    if traffic is not None:
+        out["roofline_traction"]["traffic"] = traffic
     if ttu is not None:
         out["time_to_U"] = ttu
         t64 = (out["time_to_U"].get("fp64_precond") or {}).get("time_to_U_s")
@@ -507,15 +511,21 @@ def summarize_profiles(prof_dir, commands):
     # the first elementwise dispatch is the fill (write only); the others are the copies
     fetch_factor = copy_bytes / (max(cf) * 1024.0)
     write_factor = copy_bytes / (max(cw) * 1024.0)
-    key = [k for k in pmc("apply_fetch", "FETCH_SIZE") if "k_apply<7, double>" in k][0]
-    f = pmc("apply_fetch", "FETCH_SIZE")[key]
-    w = pmc("apply_write", "WRITE_SIZE")[key]
-    fetch = float(np.mean(f)) * 1024.0 * fetch_factor
-    write = float(np.mean(w)) * 1024.0 * write_factor
+    def per_launch(name):
+        key = [k for k in pmc("apply_fetch", "FETCH_SIZE") if name in k][0]
+        f = pmc("apply_fetch", "FETCH_SIZE")[key]
+        w = pmc("apply_write", "WRITE_SIZE")[key]
+        return (f, w, float(np.mean(f)) * 1024.0 * fetch_factor, float(np.mean(w)) * 1024.0 * write_factor)
+
+    f, w, fetch, write = per_launch("k_apply<7, double>")
+    tf, tw, tfetch, twrite = per_launch("k_traction<7, double>")
     spec = W.config2()
     d = {"kernel": "k_apply<7,double>", "workload": "config2 (2000 elements, p=6)",
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
          "hbm_bytes_per_launch": fetch + write, "algorithmic_bytes_per_launch": apply_bytes(spec, 8),
+         "traction": {"kernel": "k_traction<7,double>", "fetch_bytes_per_launch": tfetch,
+                      "write_bytes_per_launch": twrite, "hbm_bytes_per_launch": tfetch + twrite,
+                      "algorithmic_bytes_per_launch": traction_bytes(spec, 8)},
          "fetch_calibration_factor": fetch_factor, "write_calibration_factor": write_factor,
          "operator_source_sha256_16": kernel_source_hash(), "commands": commands}
     json.dump(d, open(os.path.join(out_dir, "k_apply_config2_traffic.json"), "w"), indent=1)
@@ -523,6 +533,10 @@ def summarize_profiles(prof_dir, commands):
            f"FETCH_SIZE per launch {np.mean(f):.0f} KiB x {fetch_factor:.3f} = {fetch / 1e6:.2f} MB",
            f"WRITE_SIZE per launch {np.mean(w):.0f} KiB x {write_factor:.3f} = {write / 1e6:.2f} MB",
            f"algorithmic bytes per launch {apply_bytes(spec, 8) / 1e6:.2f} MB", "",
+           "The same runs, k_traction<7,double>:", "",
+           f"FETCH_SIZE per launch {np.mean(tf):.0f} KiB x {fetch_factor:.3f} = {tfetch / 1e6:.2f} MB",
+           f"WRITE_SIZE per launch {np.mean(tw):.0f} KiB x {write_factor:.3f} = {twrite / 1e6:.2f} MB",
+           f"algorithmic bytes per launch {traction_bytes(spec, 8) / 1e6:.2f} MB", "",
            "Calibration: the same counters on a plain copy of 256 MiB (bench.py --calib-copy) read "
            f"{max(cf):.0f} KiB fetched and {max(cw):.0f} KiB written per copy.", "", "Commands:", ""]
     txt += ["    " + c for c in commands.values()]
@@ -539,15 +553,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of k_apply<7,double> from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
+def measured_traffic(kernel="apply"):
+    """HBM bytes per launch of k_apply<7,double> (or, kernel="traction", of
+    k_traction<7,double>) from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "k_apply_config2_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("operator_source_sha256_16") != kernel_source_hash():
         return None
+    if kernel == "traction":
+        return d.get("traction", {}).get("hbm_bytes_per_launch")
     return d["hbm_bytes_per_launch"]
 
 
