@@ -40,17 +40,17 @@ HBM_PEAK_GBS = 8000.0
 
 # The rocprofv3 runs whose output --summarize reads (from the repository root).
 PROFILE_COMMANDS = {
-    "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run --output-format csv -- "
+    "trace": "rocprofv3 --kernel-trace --stats -d prof_out/trace -o run --output-format csv -- "
              "python3 bench.py --no-cpu --no-solve --steps 2 --reps 20 --warmup 1",
-    "apply_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/apply_fetch -o run --output-format csv -- "
+    "apply_fetch": "rocprofv3 --pmc FETCH_SIZE -d prof_out/apply_fetch -o run --output-format csv -- "
                    "python3 bench.py --no-cpu --no-solve --steps 1 --reps 4 --warmup 1",
-    "apply_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/apply_write -o run --output-format csv -- "
+    "apply_write": "rocprofv3 --pmc WRITE_SIZE -d prof_out/apply_write -o run --output-format csv -- "
                    "python3 bench.py --no-cpu --no-solve --steps 1 --reps 4 --warmup 1",
-    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copy_fetch -o run --output-format csv -- "
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -d prof_out/copy_fetch -o run --output-format csv -- "
                   "python3 bench.py --calib-copy",
-    "copy_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_write -o run --output-format csv -- "
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE -d prof_out/copy_write -o run --output-format csv -- "
                   "python3 bench.py --calib-copy",
-    "solve": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/solve -o run --output-format csv -- "
+    "solve": "rocprofv3 --kernel-trace --stats -d prof_out/solve -o run --output-format csv -- "
              "python3 bench.py --one-solve",
 }
 FP64_PEAK_TFLOPS = 78.6
