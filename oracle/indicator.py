@@ -1,0 +1,47 @@
+"""Oracle: the face-jump indicator that drives adaptive z-refinement.
+
+Test infrastructure only, like the rest of oracle/.
+
+The method is discontinuous across element faces and penalises the jump [u]
+(Sec. 2.2.4, eq. penalty), so the size of the jumps is the natural measure of
+where the discrete solution is under-resolved; Sec. 4 names adaptive mesh
+refinement as the next step.  Per element e, with the face quadrature of the
+operator (LGL weights times the surface Jacobian J^Sigma, identical on both
+sides of a conforming face):
+
+    eta_e^2 = sum over interior faces f of e   1/2 int_f |u_e - u_nb|^2 dS
+            + sum over Dirichlet faces f of e      int_f |u_e - u_b|^2 dS   (u_b = 0)
+
+Neumann faces contribute nothing.  Each interior face's integral is split
+equally between its two elements, so sum_e eta_e^2 = sum over faces of
+int |[u]|^2 dS.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .dg import _neighbour_face
+from .mesh import get_face
+
+
+def jump_indicator(prob, u):
+    """eta_e^2 for every element of the oracle Problem `prob`, u [E, 3, N, N, N]."""
+    geo, m, N = prob.geo, prob.mesh, prob.N
+    out = np.zeros(prob.E)
+    for f in range(6):
+        ws = geo.wface[f][None] * geo.jsig[:, f]          # w_face J^Sigma  [E, NN]
+        uf = get_face(u, f, N)                             # [E, 3, NN]
+        ue = _neighbour_face(prob, u, f)                   # neighbour traces (0 on boundaries)
+        interior = m.nbr[:, f] >= 0
+        dirichlet = m.bc[:, f] == 1
+        jump2 = np.sum((uf - ue) ** 2, axis=1)             # [E, NN]
+        val2 = np.sum(uf ** 2, axis=1)
+        dens = np.where(interior[:, None], 0.5 * jump2, np.where(dirichlet[:, None], val2, 0.0))
+        out += np.sum(ws * dens, axis=1)
+    return out
+
+
+def layer_indicator(prob, u):
+    """Per-layer sums of eta_e^2."""
+    eta2 = jump_indicator(prob, u)
+    return np.bincount(prob.mesh.layer, weights=eta2, minlength=prob.mesh.n_layers)
