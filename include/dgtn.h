@@ -268,6 +268,20 @@ dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const d
  * Synchronises the stream. */
 dgtn_status dgtn_energy_parts(dgtn_ctx* ctx, const double* u, double* parts, hipStream_t stream);
 
+/* Face-jump indicator for adaptive refinement (the jump [u] is what the interior
+ * penalty of Sec. 2.2.4, eq. penalty, acts on; Sec. 4 names adaptive mesh
+ * refinement as the next step).  Per element e, with the face quadrature of the
+ * operator (LGL weights times the surface Jacobian):
+ *   eta_e^2 = sum over interior faces  1/2 int |u_e - u_neighbour|^2 dS
+ *           + sum over Dirichlet faces     int |u_e|^2 dS   (homogeneous data),
+ * nothing on Neumann faces, so the element values sum to the jump integral
+ * over all faces.  u: device double, n_dof.  eta_elem: host, n_elem, element
+ * order of u (may be null); eta_layers: host, n_layers, the per-layer sums in
+ * fixed order (may be null; not both).  Lengths in the problem's units.
+ * Synchronises the stream; DGTN_ENAN if a value is not finite. */
+dgtn_status dgtn_jump_indicator(dgtn_ctx* ctx, const double* u, double* eta_elem, double* eta_layers,
+                                hipStream_t stream);
+
 /* S_x = 4 kB T sum_{k,q} phi[3 k + q] parts[3 k + q] / (pi f F0^2): the noise
  * with one loss angle per energy part of dgtn_energy_parts.  Pure host
  * function; DGTN_EINVAL for n_layers < 1, T <= 0, f <= 0 or F0 = 0. */

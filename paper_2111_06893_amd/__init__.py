@@ -254,6 +254,19 @@ class Problem:
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
         return out
 
+    def jump_indicator(self, u):
+        """Face-jump indicator of adaptive refinement: (eta_e^2 per element in the
+        element order of u, their per-layer sums), numpy."""
+        import torch
+        self._ensure()
+        self._check_field(u, torch.float64)
+        eta = np.zeros(self.info.n_elem)
+        lay = np.zeros(self.n_layers)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(self.lib.dgtn_jump_indicator(self.ctx, ctypes.c_void_p(u.data_ptr()), eta.ctypes.data_as(dp),
+                                           lay.ctypes.data_as(dp), self._stream()))
+        return eta, lay
+
     def energy_parts(self, u):
         """[n_layers, 3] layer energies split by modulus (isotropic: bulk, shear, 0;
         cubic: c11, c12, c44 parts), numpy, J."""

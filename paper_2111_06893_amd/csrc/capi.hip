@@ -342,6 +342,27 @@ dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, hipStrea
     return DGTN_OK;
 }
 
+dgtn_status dgtn_jump_indicator(dgtn_ctx* c, const double* u, double* eta_elem, double* eta_layers, hipStream_t s) {
+    if (!c || !u || (!eta_elem && !eta_layers)) { set_error("null argument"); return DGTN_EINVAL; }
+    if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
+    const Level& L = c->levels[0];
+    auto v = view_of<double>(c, L);
+    double* d = reinterpret_cast<double*>(c->ws + c->off_Ue);  // per-element scratch of the energies
+    HIP_CHECK(launch_jump_indicator(v, u, d, s));
+    std::vector<double> h(L.E);
+    HIP_CHECK(hipMemcpyAsync(h.data(), d, 8 * (size_t)L.E, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (int e = 0; e < L.E; ++e)
+        if (!std::isfinite(h[e])) { set_error("non-finite indicator"); return DGTN_ENAN; }
+    if (eta_elem) std::copy(h.begin(), h.end(), eta_elem);
+    if (eta_layers) {
+        const int nl = (int)c->prob.layers.size();
+        for (int k = 0; k < nl; ++k) eta_layers[k] = 0;
+        for (int e = 0; e < L.E; ++e) eta_layers[L.zlayer[e / L.n_cols]] += h[e];  // fixed order
+    }
+    return DGTN_OK;
+}
+
 dgtn_status dgtn_energy_parts(dgtn_ctx* c, const double* u, double* parts, hipStream_t s) {
     if (!c || !u || !parts) { set_error("null argument"); return DGTN_EINVAL; }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }

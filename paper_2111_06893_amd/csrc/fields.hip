@@ -207,6 +207,70 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy_grad(LevelView<doub
     }
 }
 
+// Face-jump indicator of adaptive refinement: eta_e^2 = sum over the element's
+// faces of 1/2 int |u_e - u_nb|^2 dS on interior faces and int |u_e|^2 dS on
+// Dirichlet faces (homogeneous data), none on Neumann faces, with the face
+// quadrature of the operator (w_face J^Sigma).  The jump is what the interior
+// penalty of eq. penalty acts on; Sec. 4 names adaptive refinement as the next
+// step.  One workgroup per element: wave 0 resolves the face records, one lane
+// per face node, a fixed-order sum.
+template <int N>
+__global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<double> L,
+                                                                     const double* __restrict__ u,
+                                                                     double* __restrict__ eta) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = line_threads<N>();
+    __shared__ FaceInfo<double> sface[6];
+    __shared__ double sown[5];
+    __shared__ double red[NT / 64];
+    const int e = L.e0 + blockIdx.x;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int col = e % L.n_cols, iz = e / L.n_cols;
+    if (tid < 64) load_faces<N>(L, col, iz, tid, sface, sown);
+    __syncthreads();
+    double dens = 0;
+    if (tid < 6 * N2) {
+        const int f = tid / N2, fi = tid % N2;
+        int i, j, k;
+        face_node<N>(f, fi, i, j, k);
+        const FaceInfo<double>& fo = sface[f];
+        const double det2 = L.geo2[(size_t)col * 5 * N2 + 4 * N2 + j * N + i];
+        double n[3], amag;
+        face_frame<N>(L, col, f, i, j, n, amag);
+        const double hz = sown[3];
+        const double ws = f >= 4 ? L.w[i] * L.w[j] * det2
+                        : f < 2  ? L.w[j] * L.w[k] * 0.5 * hz * det2 * amag
+                                 : L.w[i] * L.w[k] * 0.5 * hz * det2 * amag;
+        const double* ue = u + (size_t)e * 3 * N3 + k * N2 + j * N + i;
+        if (fo.bc == 0) {
+            int i2, j2, k2;
+            const Nbr nb{fo.e, fo.f, fo.flip, 0};
+            matching_node<N>(f, nb, i, j, k, i2, j2, k2);
+            const double* un = u + (size_t)fo.e * 3 * N3 + k2 * N2 + j2 * N + i2;
+            double s2 = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double d = ue[c * N3] - un[c * N3];
+                s2 += d * d;
+            }
+            dens = 0.5 * ws * s2;
+        } else if (fo.bc == DGTN_BC_DIRICHLET) {
+            double s2 = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s2 += ue[c * N3] * ue[c * N3];
+            dens = ws * s2;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) dens += __shfl_xor(dens, off);
+    if (lane == 0) red[wave] = dens;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        eta[blockIdx.x] = t;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
@@ -214,6 +278,14 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         hipLaunchKernelGGL((k_rhs<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, xy, F0, r0, xc, yc, mode, b);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, double* eta, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_jump_indicator<NN>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, eta);
         return hipGetLastError();
     });
 }
