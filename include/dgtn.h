@@ -275,11 +275,16 @@ dgtn_status dgtn_energy_parts(dgtn_ctx* ctx, const double* u, double* parts, hip
  *   eta_e^2 = sum over interior faces  1/2 int |u_e - u_neighbour|^2 dS
  *           + sum over Dirichlet faces     int |u_e|^2 dS   (homogeneous data),
  * nothing on Neumann faces, so the element values sum to the jump integral
- * over all faces.  u: device double, n_dof.  eta_elem: host, n_elem, element
+ * over all faces.  faces selects the face families summed: DGTN_FACES_SIDE (the
+ * four faces across the disk, logical xi and eta), DGTN_FACES_Z (the two faces
+ * across the layers, logical zeta: the jumps that refinement in z reduces) or
+ * DGTN_FACES_ALL; other values give DGTN_EINVAL.  u: device double, n_dof.
+ * eta_elem: host, n_elem, element
  * order of u (may be null); eta_layers: host, n_layers, the per-layer sums in
  * fixed order (may be null; not both).  Lengths in the problem's units.
  * Synchronises the stream; DGTN_ENAN if a value is not finite. */
-dgtn_status dgtn_jump_indicator(dgtn_ctx* ctx, const double* u, double* eta_elem, double* eta_layers,
+enum { DGTN_FACES_SIDE = 1, DGTN_FACES_Z = 2, DGTN_FACES_ALL = 3 };
+dgtn_status dgtn_jump_indicator(dgtn_ctx* ctx, const double* u, int faces, double* eta_elem, double* eta_layers,
                                 hipStream_t stream);
 
 /* S_x = 4 kB T sum_{k,q} phi[3 k + q] parts[3 k + q] / (pi f F0^2): the noise

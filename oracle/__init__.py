@@ -18,6 +18,8 @@ arithmetic written to be read against the paper:
                 (Sec. 2.2.2 - 2.2.4, eqs. dg_residuals, numflux, penalty, bc),
                 load vector, energies
 * ``solve``     dense and conjugate-gradient solves (Sec. 2.3)
+* ``indicator`` face-jump indicator of adaptive refinement (the jump the
+                penalty of eq. penalty acts on; Sec. 4)
 * ``physics``   Levin noise formula and closed forms (Sec. 2.1)
 * ``slab``      semi-analytic layered-slab energies per Fourier mode, used only
                 to pin the physics

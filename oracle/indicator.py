@@ -14,7 +14,9 @@ sides of a conforming face):
 
 Neumann faces contribute nothing.  Each interior face's integral is split
 equally between its two elements, so sum_e eta_e^2 = sum over faces of
-int |[u]|^2 dS.
+int |[u]|^2 dS.  The sum may be restricted to one family of faces: the side
+faces across the disk or the z-faces across the layers; refinement in z acts
+on the jumps of the latter only.
 """
 from __future__ import annotations
 
@@ -24,11 +26,17 @@ from .dg import _neighbour_face
 from .mesh import get_face
 
 
-def jump_indicator(prob, u):
-    """eta_e^2 for every element of the oracle Problem `prob`, u [E, 3, N, N, N]."""
+FACES = {"all": range(6), "side": range(4), "z": range(4, 6)}
+
+
+def jump_indicator(prob, u, faces="all"):
+    """eta_e^2 for every element of the oracle Problem `prob`, u [E, 3, N, N, N],
+    over the element's faces of the family `faces`: "side" (the four faces across
+    the disk, logical xi and eta), "z" (the two faces across the layers, logical
+    zeta, where z-refinement acts) or "all"."""
     geo, m, N = prob.geo, prob.mesh, prob.N
     out = np.zeros(prob.E)
-    for f in range(6):
+    for f in FACES[faces]:
         ws = geo.wface[f][None] * geo.jsig[:, f]          # w_face J^Sigma  [E, NN]
         uf = get_face(u, f, N)                             # [E, 3, NN]
         ue = _neighbour_face(prob, u, f)                   # neighbour traces (0 on boundaries)
@@ -41,7 +49,7 @@ def jump_indicator(prob, u):
     return out
 
 
-def layer_indicator(prob, u):
+def layer_indicator(prob, u, faces="all"):
     """Per-layer sums of eta_e^2."""
-    eta2 = jump_indicator(prob, u)
+    eta2 = jump_indicator(prob, u, faces)
     return np.bincount(prob.mesh.layer, weights=eta2, minlength=prob.mesh.n_layers)

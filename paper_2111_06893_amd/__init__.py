@@ -254,16 +254,18 @@ class Problem:
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
         return out
 
-    def jump_indicator(self, u):
+    def jump_indicator(self, u, faces="all"):
         """Face-jump indicator of adaptive refinement: (eta_e^2 per element in the
-        element order of u, their per-layer sums), numpy."""
+        element order of u, their per-layer sums), numpy, over the face family
+        `faces`: "side", "z" or "all"."""
         import torch
         self._ensure()
         self._check_field(u, torch.float64)
         eta = np.zeros(self.info.n_elem)
         lay = np.zeros(self.n_layers)
         dp = ctypes.POINTER(ctypes.c_double)
-        check(self.lib.dgtn_jump_indicator(self.ctx, ctypes.c_void_p(u.data_ptr()), eta.ctypes.data_as(dp),
+        which = {"side": 1, "z": 2, "all": 3}[faces]
+        check(self.lib.dgtn_jump_indicator(self.ctx, ctypes.c_void_p(u.data_ptr()), which, eta.ctypes.data_as(dp),
                                            lay.ctypes.data_as(dp), self._stream()))
         return eta, lay
 

@@ -65,7 +65,7 @@ _SIGS = {
     "dgtn_grad": (c_int, [c_void_p, c_void_p, c_void_p, P(c_double), c_int, P(Param), P(c_double), c_void_p]),
     "dgtn_noise_psd": (c_int, [P(c_double), P(c_double), c_int, c_double, c_double, c_double, P(c_double)]),
     "dgtn_energy_parts": (c_int, [c_void_p, c_void_p, P(c_double), c_void_p]),
-    "dgtn_jump_indicator": (c_int, [c_void_p, c_void_p, P(c_double), P(c_double), c_void_p]),
+    "dgtn_jump_indicator": (c_int, [c_void_p, c_void_p, c_int, P(c_double), P(c_double), c_void_p]),
     "dgtn_noise_psd_parts": (c_int, [P(c_double), P(c_double), c_int, c_double, c_double, c_double,
                                      P(c_double)]),
     "dgtn_node_coords": (c_int, [c_void_p, P(c_double)]),

@@ -1,0 +1,104 @@
+"""Adaptive refinement across the layers, driven by the face-jump indicator.
+
+Sec. 4 names adaptive mesh refinement as the way to reach a given accuracy with
+fewer unknowns.  The mesh here is a 2D disk (or box) mesh extruded through the
+layers, so refining in z (more elements across a layer's thickness, same grading
+ratio) keeps every face conforming and needs no mortar projections; refinement
+across the disk or per-element degrees would (not built).
+
+One step:
+  1. solve A u = b on the device and take the layer energies U_k;
+  2. eta_e^2, the face-jump indicator of dgtn_jump_indicator over the z-faces
+     (the jumps between z-elements and on the fixed face: the side-face jumps
+     measure the resolution across the disk, which refinement in z leaves as it
+     is), summed per layer;
+  3. mark the fewest layers whose indicators hold a fraction theta of the total
+     (bulk marking, largest first);
+  4. multiply their element counts across the thickness by `factor`.
+The jumps are what the interior penalty acts on, and they vanish for a field the
+discrete space represents exactly, so they measure where u is under-resolved.
+"""
+from __future__ import annotations
+
+import copy
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import Problem, default_opts
+
+__all__ = ["mark_layers", "refine_layers", "AdaptStep", "adapt"]
+
+
+def mark_layers(eta_layers: Sequence[float], theta: float = 0.5) -> List[int]:
+    """Indices of the fewest layers whose indicator sum reaches theta times the
+    total, largest first (ties keep the lower index)."""
+    eta = np.asarray(eta_layers, dtype=np.float64)
+    if eta.ndim != 1 or eta.size == 0 or np.any(eta < 0) or not 0 < theta <= 1:
+        raise ValueError("non-negative layer indicators and 0 < theta <= 1 expected")
+    total = eta.sum()
+    if total == 0:
+        return []
+    order = np.argsort(-eta, kind="stable")
+    acc, out = 0.0, []
+    for k in order:
+        out.append(int(k))
+        acc += eta[k]
+        if acc >= theta * total:
+            break
+    return sorted(out)
+
+
+def refine_layers(spec: dict, layers: Sequence[int], factor: int = 2, max_elem: Optional[int] = None) -> dict:
+    """A copy of spec whose listed layers have `factor` times as many elements
+    across their thickness (capped at max_elem)."""
+    if factor < 2:
+        raise ValueError("factor must be at least 2")
+    s = copy.deepcopy(spec)
+    for k in layers:
+        n = s["layers"][k]["n_elem"] * factor
+        s["layers"][k]["n_elem"] = n if max_elem is None else min(n, max_elem)
+    return s
+
+
+@dataclass
+class AdaptStep:
+    spec: dict                 # the mesh this step solved on
+    n_dof: int
+    U: np.ndarray              # layer energies (J)
+    eta_layers: np.ndarray     # per-layer indicator sums
+    marked: List[int]          # layers refined for the next step
+    iters: int                 # Krylov iterations of the solve
+
+
+def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=None, tol: Optional[float] = None,
+          max_elem: Optional[int] = 64) -> List[AdaptStep]:
+    """Solve-estimate-mark-refine for `steps` meshes (fewer if the total
+    indicator drops to tol or no layer can be refined further)."""
+    o = opts if opts is not None else default_opts(32, rtol=1e-10)
+    s = copy.deepcopy(spec)
+    out: List[AdaptStep] = []
+    for it in range(steps):
+        P = Problem(s)
+        try:
+            # finer meshes raise the penalty and with it the FP64 residual floor: a
+            # solve that stagnates there is accepted (the energies are quadratic in
+            # the solution error), one that stalls far above it is not
+            u, st = P.solve(opts=o, raise_on_noconv=False)
+            if not st.converged and st.rel_res > 1e-6:
+                raise RuntimeError(f"adaptive step {it}: solve stalled at relative residual {st.rel_res:.3e}")
+            U = P.energy(u)
+            _, lay = P.jump_indicator(u, faces="z")
+            n_dof = int(P.info.n_dof)
+        finally:
+            P.close()
+        last = it == steps - 1 or (tol is not None and lay.sum() <= tol)
+        marked = [] if last else mark_layers(lay, theta)
+        if max_elem is not None:
+            marked = [k for k in marked if s["layers"][k]["n_elem"] < max_elem]
+        out.append(AdaptStep(s, n_dof, U, lay, marked, int(st.iters)))
+        if last or not marked:
+            break
+        s = refine_layers(s, marked, factor, max_elem)
+    return out

@@ -342,13 +342,15 @@ dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, hipStrea
     return DGTN_OK;
 }
 
-dgtn_status dgtn_jump_indicator(dgtn_ctx* c, const double* u, double* eta_elem, double* eta_layers, hipStream_t s) {
+dgtn_status dgtn_jump_indicator(dgtn_ctx* c, const double* u, int faces, double* eta_elem, double* eta_layers,
+                                hipStream_t s) {
     if (!c || !u || (!eta_elem && !eta_layers)) { set_error("null argument"); return DGTN_EINVAL; }
+    if (faces < DGTN_FACES_SIDE || faces > DGTN_FACES_ALL) { set_error("faces must be 1, 2 or 3"); return DGTN_EINVAL; }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     const Level& L = c->levels[0];
     auto v = view_of<double>(c, L);
     double* d = reinterpret_cast<double*>(c->ws + c->off_Ue);  // per-element scratch of the energies
-    HIP_CHECK(launch_jump_indicator(v, u, d, s));
+    HIP_CHECK(launch_jump_indicator(v, u, faces, d, s));
     std::vector<double> h(L.E);
     HIP_CHECK(hipMemcpyAsync(h.data(), d, 8 * (size_t)L.E, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));

@@ -65,7 +65,8 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
 template <typename R>
 hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s);
 hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s);
-hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, double* eta, hipStream_t s);
+hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, int which, double* eta,
+                                 hipStream_t s);
 hipError_t launch_energy_grad(const LevelView<double>& L, const double* u, const double* wz, double* g, double scale,
                               hipStream_t s);
 template <>

@@ -212,11 +212,12 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy_grad(LevelView<doub
 // Dirichlet faces (homogeneous data), none on Neumann faces, with the face
 // quadrature of the operator (w_face J^Sigma).  The jump is what the interior
 // penalty of eq. penalty acts on; Sec. 4 names adaptive refinement as the next
-// step.  One workgroup per element: wave 0 resolves the face records, one lane
-// per face node, a fixed-order sum.
+// step.  The sum may be restricted to the side faces or to the z-faces, where
+// refinement across the layers acts.  One workgroup per element: wave 0
+// resolves the face records, one lane per face node, a fixed-order sum.
 template <int N>
 __global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<double> L,
-                                                                     const double* __restrict__ u,
+                                                                     const double* __restrict__ u, int which,
                                                                      double* __restrict__ eta) {
     constexpr int N2 = N * N, N3 = N2 * N, NT = line_threads<N>();
     __shared__ FaceInfo<double> sface[6];
@@ -228,7 +229,8 @@ __global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<
     if (tid < 64) load_faces<N>(L, col, iz, tid, sface, sown);
     __syncthreads();
     double dens = 0;
-    if (tid < 6 * N2) {
+    // which: 1 the side faces (logical xi, eta), 2 the z-faces (zeta), 3 both
+    if (tid < 6 * N2 && (which & (tid / N2 < 4 ? 1 : 2))) {
         const int f = tid / N2, fi = tid % N2;
         int i, j, k;
         face_node<N>(f, fi, i, j, k);
@@ -282,10 +284,11 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
     });
 }
 
-hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, double* eta, hipStream_t s) {
+hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, int which, double* eta,
+                                 hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_jump_indicator<NN>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, eta);
+        hipLaunchKernelGGL((k_jump_indicator<NN>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, which, eta);
         return hipGetLastError();
     });
 }

@@ -1,7 +1,7 @@
 """GPU parity of the face-jump indicator (dgtn_jump_indicator) with the oracle's
 (oracle/indicator.py, pinned in tests/test_oracle_indicator.py): every element's
-value and the per-layer sums on the same seeded fields, FP64 to 1e-12 of the
-largest value; boxes at p = 1, 3, 7 (Dirichlet, pressure and free faces), the
+value and the per-layer sums on the same seeded fields, over all faces, the
+side faces and the z-faces, FP64 to 1e-12 of the largest value; boxes at p = 1, 3, 7 (Dirichlet, pressure and free faces), the
 curved cylinder, and the thin-coating workload at full size."""
 import numpy as np
 import pytest
@@ -31,12 +31,13 @@ def test_indicator_matches_oracle(name):
     print(f"[indicator] {name}", flush=True)
     u = W.random_field(spec, seed=11)
     P = dgtn.Problem(spec)
-    eta, lay = P.jump_indicator(torch.from_numpy(u).to("cuda"))
     O = dg.Problem(spec)
-    ref = indicator.jump_indicator(O, u)
-    scale = np.abs(ref).max()
-    assert np.abs(eta - ref).max() <= 1e-12 * scale
-    np.testing.assert_allclose(lay, indicator.layer_indicator(O, u), rtol=1e-12)
+    ud = torch.from_numpy(u).to("cuda")
+    for faces in ("all", "side", "z"):
+        eta, lay = P.jump_indicator(ud, faces)
+        ref = indicator.jump_indicator(O, u, faces)
+        assert np.abs(eta - ref).max() <= 1e-12 * np.abs(ref).max(), faces
+        np.testing.assert_allclose(lay, indicator.layer_indicator(O, u, faces), rtol=1e-12)
 
 
 def test_indicator_of_a_linear_field_is_the_fixed_face_integral():

@@ -84,3 +84,31 @@ def test_scaling_and_layer_sums():
     e1 = indicator.jump_indicator(P, u)
     np.testing.assert_allclose(indicator.jump_indicator(P, -3.0 * u), 9.0 * e1, rtol=1e-14)
     np.testing.assert_allclose(indicator.layer_indicator(P, u).sum(), e1.sum(), rtol=1e-14)
+
+
+def test_face_families_add_up_and_separate():
+    spec = layered_box()
+    P = dg.Problem(spec)
+    u = np.random.default_rng(8).standard_normal(P.shape)
+    all_ = indicator.jump_indicator(P, u)
+    np.testing.assert_allclose(indicator.jump_indicator(P, u, "side") + indicator.jump_indicator(P, u, "z"), all_,
+                               rtol=1e-14)
+    # a step across the layer interface jumps on z-faces only
+    c = 0.7
+    v = np.zeros(P.shape)
+    v[P.mesh.layer == 0, 1] = c
+    assert np.abs(indicator.jump_indicator(P, v, "side")).max() == 0.0
+    assert indicator.jump_indicator(P, v, "z").sum() == pytest.approx(c * c * spec["Lx"] * spec["Ly"], rel=1e-13)
+    # a step across the vertical plane x = 0 (between the two columns along x): its
+    # interior jump lies on side faces only
+    x = P.node_xyz()[:, 0]
+    w = np.zeros(P.shape)
+    right = x.mean(axis=(1, 2, 3)) > 0
+    w[right, 2] = c
+    # its z-faces carry only the fixed-face term of the right half, c^2 (Lx / 2) Ly
+    wz = indicator.jump_indicator(P, w, "z")
+    on_bottom = (P.mesh.bc == 1).any(axis=1)
+    assert np.abs(wz[~on_bottom]).max() == 0.0
+    assert wz.sum() == pytest.approx(c * c * 0.5 * spec["Lx"] * spec["Ly"], rel=1e-13)
+    H = P.node_xyz()[:, 2].max() - P.node_xyz()[:, 2].min()
+    assert indicator.jump_indicator(P, w, "side").sum() == pytest.approx(c * c * spec["Ly"] * H, rel=1e-13)
