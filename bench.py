@@ -392,6 +392,7 @@ def main():
         torch.cuda.empty_cache()
         out["forty_layer_adjoint"] = forty_layer_adjoint(log)
         out["design_loop"] = design_loop(log)
+        out["adaptive_refinement"] = adaptive_refinement(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     out["paper_cpu_timings"] = PAPER_CPU_TIMINGS
@@ -418,6 +419,29 @@ def design_loop(log):
     return {"workload": "beam centre on xc - yc = 0.2 minimising S_x, five-block cylinder, 40 elements, p=5",
             "x": r.x.tolist(), "expected": [0.1, -0.1], "evaluations": r.n_evals, "seconds": dt,
             "S_x": r.fun}
+
+
+def adaptive_refinement(log, steps=3):
+    """Untimed record of adaptive refinement across the layers: the coated
+    cylinder (coating 1e-3 R and substrate, one element each across their
+    thickness, 20 columns, p = 3) through `steps` solve / z-face indicator /
+    mark / refine steps."""
+    import torch
+    import paper_2111_06893_amd as dgtn
+    from paper_2111_06893_amd import adapt
+    spec = W.config4()
+    spec["p"] = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = adapt.adapt(spec, steps=steps, theta=0.6, opts=dgtn.default_opts(32, rtol=1e-9, max_iter=5000))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = [{"n_elem_per_layer": [l["n_elem"] for l in r.spec["layers"]], "n_dof": r.n_dof,
+            "U_layers": r.U.tolist(), "eta_z_layers": r.eta_layers.tolist(), "marked": r.marked,
+            "iters": r.iters} for r in rec]
+    log(f"adaptive refinement: {[o['n_elem_per_layer'] for o in out]}, {dt:.2f} s")
+    return {"workload": "coated cylinder (coating 1e-3 R, 20 columns, p=3), refinement across the layers",
+            "steps": out, "seconds": dt}
 
 
 def forty_layer_adjoint(log, reps=3):
