@@ -3,8 +3,9 @@
 Sec. 4 names adaptive mesh refinement as the way to reach a given accuracy with
 fewer unknowns.  The mesh here is a 2D disk (or box) mesh extruded through the
 layers, so refining in z (more elements across a layer's thickness, same grading
-ratio) keeps every face conforming and needs no mortar projections; refinement
-across the disk or per-element degrees would (not built).
+ratio) keeps every face conforming and needs no mortar projections, and so does
+refining the whole disk mesh at once; local refinement across the disk or
+per-element degrees would need them (not built).
 
 One step:
   1. solve A u = b on the device and take the layer energies U_k;
@@ -28,7 +29,7 @@ import numpy as np
 
 from . import Problem, default_opts
 
-__all__ = ["mark_layers", "refine_layers", "AdaptStep", "adapt"]
+__all__ = ["mark_layers", "refine_layers", "refine_disk", "AdaptStep", "adapt"]
 
 
 def mark_layers(eta_layers: Sequence[float], theta: float = 0.5) -> List[int]:
@@ -62,20 +63,38 @@ def refine_layers(spec: dict, layers: Sequence[int], factor: int = 2, max_elem: 
     return s
 
 
+def refine_disk(spec: dict) -> dict:
+    """A copy of spec refined once across the disk, everywhere: the cylinder's
+    disk mesh one level finer (four times the columns), the box's columns halved
+    in both directions.  Conforming, like refinement in z."""
+    s = copy.deepcopy(spec)
+    if s["domain"] == "cylinder":
+        s["refine"] += 1
+    else:
+        s["nx"] *= 2
+        s["ny"] *= 2
+    return s
+
+
 @dataclass
 class AdaptStep:
     spec: dict                 # the mesh this step solved on
     n_dof: int
     U: np.ndarray              # layer energies (J)
     eta_layers: np.ndarray     # per-layer indicator sums
-    marked: List[int]          # layers refined for the next step
+    marked: List[int]          # layers refined in z for the next step
     iters: int                 # Krylov iterations of the solve
+    eta_side: float = 0.0      # total side-face indicator
+    action: str = ""           # "z", "disk" or "" (last step)
 
 
 def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=None, tol: Optional[float] = None,
-          max_elem: Optional[int] = 64) -> List[AdaptStep]:
+          max_elem: Optional[int] = 64, disk: bool = False) -> List[AdaptStep]:
     """Solve-estimate-mark-refine for `steps` meshes (fewer if the total
-    indicator drops to tol or no layer can be refined further)."""
+    z-face indicator drops to tol or no layer can be refined further).  With
+    disk=True a step whose side-face jumps outweigh its z-face jumps refines
+    across the disk instead (refine_disk), so the loop follows the direction
+    in which the solution is under-resolved."""
     o = opts if opts is not None else default_opts(32, rtol=1e-10)
     s = copy.deepcopy(spec)
     out: List[AdaptStep] = []
@@ -90,14 +109,19 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
                 raise RuntimeError(f"adaptive step {it}: solve stalled at relative residual {st.rel_res:.3e}")
             U = P.energy(u)
             _, lay = P.jump_indicator(u, faces="z")
+            side = float(P.jump_indicator(u, faces="side")[1].sum()) if disk else 0.0
             n_dof = int(P.info.n_dof)
         finally:
             P.close()
         last = it == steps - 1 or (tol is not None and lay.sum() <= tol)
+        if not last and disk and side > lay.sum():
+            out.append(AdaptStep(s, n_dof, U, lay, [], int(st.iters), side, "disk"))
+            s = refine_disk(s)
+            continue
         marked = [] if last else mark_layers(lay, theta)
         if max_elem is not None:
             marked = [k for k in marked if s["layers"][k]["n_elem"] < max_elem]
-        out.append(AdaptStep(s, n_dof, U, lay, marked, int(st.iters)))
+        out.append(AdaptStep(s, n_dof, U, lay, marked, int(st.iters), side, "z" if marked else ""))
         if last or not marked:
             break
         s = refine_layers(s, marked, factor, max_elem)

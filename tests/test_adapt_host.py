@@ -28,3 +28,12 @@ def test_refine_layers_multiplies_marked_counts_only():
     assert all(l["n_elem"] <= 3 for l in capped["layers"])
     with pytest.raises(ValueError):
         adapt.refine_layers(spec, [0], factor=1)
+
+
+def test_refine_disk_is_global_and_conforming():
+    cyl = W.config1()
+    assert adapt.refine_disk(cyl)["refine"] == cyl["refine"] + 1
+    assert W.n_columns(adapt.refine_disk(cyl)) == 4 * W.n_columns(cyl)
+    box = W.box(nx=2, ny=3)
+    b2 = adapt.refine_disk(box)
+    assert (b2["nx"], b2["ny"]) == (4, 6) and box["nx"] == 2

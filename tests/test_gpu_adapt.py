@@ -56,3 +56,26 @@ def test_adaptive_z_refinement_converges_to_the_z_refined_energy():
     e_uniform = abs(U_uniform - Uref) / Uref
     assert steps[3].n_dof < 1.2 * n_uniform, (steps[3].n_dof, n_uniform)
     assert err[3] < 0.5 * e_uniform, (err[3], e_uniform)
+
+
+def test_adaptive_loop_refines_across_the_disk_when_side_jumps_dominate():
+    # fine across the layers, two by two columns across the disk: the side-face
+    # jumps dominate, the loop refines the whole disk (conforming) and the energy
+    # converges to that of sixteen by sixteen columns with the same layers
+    # (observed errors 0.47, 0.16, 5.9e-4)
+    print("[adapt] refinement across the disk", flush=True)
+
+    def box(n):
+        s = _coarse()
+        s["nx"] = s["ny"] = n
+        s["layers"][0]["n_elem"], s["layers"][1]["n_elem"] = 2, 8
+        return s
+
+    opts = dgtn.default_opts(64, rtol=1e-10, max_iter=20000)
+    steps = adapt.adapt(box(2), steps=3, theta=0.6, opts=opts, disk=True)
+    assert [st.action for st in steps] == ["disk", "disk", ""]
+    assert [st.spec["nx"] for st in steps] == [2, 4, 8]
+    assert all(st.eta_side > st.eta_layers.sum() for st in steps[:2])
+    Uref, _ = _energy(box(16), opts)
+    err = [abs(st.U.sum() - Uref) / Uref for st in steps]
+    assert all(b < 0.5 * a for a, b in zip(err, err[1:])), err
