@@ -53,3 +53,21 @@ def test_indicator_of_a_linear_field_is_the_fixed_face_integral():
     exact = sum(a[k] ** 2 * Lx ** 3 * Ly / 12 + b[k] ** 2 * Lx * Ly ** 3 / 12 + c0[k] ** 2 * Lx * Ly
                 for k in range(3))
     assert eta.sum() == pytest.approx(exact, rel=1e-12)
+
+
+def test_indicator_rejects_bad_arguments():
+    import ctypes
+    spec = _box(1)
+    P = dgtn.Problem(spec)
+    u = torch.from_numpy(W.random_field(spec, seed=2)).to("cuda")
+    P.jump_indicator(u)      # binds the workspace
+    eta = np.zeros(P.info.n_elem)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for faces in (0, 4, -1):
+        st = P.lib.dgtn_jump_indicator(P.ctx, ctypes.c_void_p(u.data_ptr()), faces, eta.ctypes.data_as(dp), None,
+                                       P._stream())
+        assert st == -1, (faces, st)                  # DGTN_EINVAL
+    st = P.lib.dgtn_jump_indicator(P.ctx, ctypes.c_void_p(u.data_ptr()), 3, None, None, P._stream())
+    assert st == -1
+    with pytest.raises(KeyError):
+        P.jump_indicator(u, "top")
