@@ -2,9 +2,9 @@
 
 Sec. 4 names adaptive mesh refinement as the way to reach a given accuracy with
 fewer unknowns.  The mesh here is a 2D disk (or box) mesh extruded through the
-layers, so refining in z (more elements across a layer's thickness, same grading
-ratio) keeps every face conforming and needs no mortar projections, and so does
-refining the whole disk mesh at once; local refinement across the disk or
+layers, so refining in z (more elements across a layer's thickness, each old
+element split into graded new ones) keeps every face conforming and needs no
+mortar projections, and so does refining the whole disk mesh at once; local refinement across the disk or
 per-element degrees would need them (not built).
 
 One step:
@@ -15,7 +15,9 @@ One step:
      is), summed per layer;
   3. mark the fewest layers whose indicators hold a fraction theta of the total
      (bulk marking, largest first);
-  4. multiply their element counts across the thickness by `factor`.
+  4. multiply their element counts across the thickness by `factor`, splitting
+     every element of a graded layer into `factor` geometrically graded ones, so
+     the new z-faces include the old ones (the refined mesh nests the old).
 The jumps are what the interior penalty acts on, and they vanish for a field the
 discrete space represents exactly, so they measure where u is under-resolved.
 """
@@ -53,13 +55,23 @@ def mark_layers(eta_layers: Sequence[float], theta: float = 0.5) -> List[int]:
 
 def refine_layers(spec: dict, layers: Sequence[int], factor: int = 2, max_elem: Optional[int] = None) -> dict:
     """A copy of spec whose listed layers have `factor` times as many elements
-    across their thickness (capped at max_elem)."""
+    across their thickness.
+
+    A layer of n elements with growth factor q between consecutive element
+    thicknesses becomes n * factor elements with growth factor q**(1/factor):
+    the `factor` new elements inside an old one then have the old one's
+    thickness between them, so every old z-face is kept.  A layer that would
+    exceed max_elem elements is left as it is (a partial split would not nest)."""
     if factor < 2:
         raise ValueError("factor must be at least 2")
     s = copy.deepcopy(spec)
     for k in layers:
-        n = s["layers"][k]["n_elem"] * factor
-        s["layers"][k]["n_elem"] = n if max_elem is None else min(n, max_elem)
+        lay = s["layers"][k]
+        n = lay["n_elem"] * factor
+        if max_elem is not None and n > max_elem:
+            continue
+        lay["n_elem"] = n
+        lay["ratio"] = float(lay["ratio"]) ** (1.0 / factor)
     return s
 
 
@@ -84,17 +96,23 @@ class AdaptStep:
     eta_layers: np.ndarray     # per-layer indicator sums
     marked: List[int]          # layers refined in z for the next step
     iters: int                 # Krylov iterations of the solve
+    rel_res: float = 0.0       # final true relative residual of the solve
     eta_side: float = 0.0      # total side-face indicator
     action: str = ""           # "z", "disk" or "" (last step)
 
 
 def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=None, tol: Optional[float] = None,
-          max_elem: Optional[int] = 64, disk: bool = False) -> List[AdaptStep]:
+          max_elem: Optional[int] = 64, disk: bool = False, max_dof: Optional[int] = 50_000_000,
+          max_rel_res: float = 1e-8) -> List[AdaptStep]:
     """Solve-estimate-mark-refine for `steps` meshes (fewer if the total
-    z-face indicator drops to tol or no layer can be refined further).  With
-    disk=True a step whose side-face jumps outweigh its z-face jumps refines
-    across the disk instead (refine_disk), so the loop follows the direction
-    in which the solution is under-resolved."""
+    z-face indicator drops to tol, no layer can be refined further, or the
+    next mesh would exceed max_dof unknowns).  With disk=True a step whose
+    side-face jumps outweigh its z-face jumps refines across the disk instead
+    (refine_disk), so the loop follows the direction in which the solution is
+    under-resolved.  A solve that stops above rtol (at the FP64 residual floor
+    of a finer mesh) is accepted up to the relative residual max_rel_res, which
+    each step records: the layer energies are not stationary in u, so their
+    error is of first order in the residual."""
     o = opts if opts is not None else default_opts(32, rtol=1e-10)
     s = copy.deepcopy(spec)
     out: List[AdaptStep] = []
@@ -102,10 +120,11 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
         P = Problem(s)
         try:
             # finer meshes raise the penalty and with it the FP64 residual floor: a
-            # solve that stagnates there is accepted (the energies are quadratic in
-            # the solution error), one that stalls far above it is not
+            # solve that stagnates there is accepted up to max_rel_res and its
+            # residual recorded, since the layer energies carry an error of first
+            # order in it
             u, st = P.solve(opts=o, raise_on_noconv=False)
-            if not st.converged and st.rel_res > 1e-6:
+            if not st.converged and st.rel_res > max_rel_res:
                 raise RuntimeError(f"adaptive step {it}: solve stalled at relative residual {st.rel_res:.3e}")
             U = P.energy(u)
             _, lay = P.jump_indicator(u, faces="z")
@@ -114,15 +133,28 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
         finally:
             P.close()
         last = it == steps - 1 or (tol is not None and lay.sum() <= tol)
+        rr = float(st.rel_res)
         if not last and disk and side > lay.sum():
-            out.append(AdaptStep(s, n_dof, U, lay, [], int(st.iters), side, "disk"))
-            s = refine_disk(s)
-            continue
+            nxt = refine_disk(s)
+            if max_dof is None or _n_dof(nxt) <= max_dof:
+                out.append(AdaptStep(s, n_dof, U, lay, [], int(st.iters), rr, side, "disk"))
+                s = nxt
+                continue
+            last = True
         marked = [] if last else mark_layers(lay, theta)
         if max_elem is not None:
-            marked = [k for k in marked if s["layers"][k]["n_elem"] < max_elem]
-        out.append(AdaptStep(s, n_dof, U, lay, marked, int(st.iters), side, "z" if marked else ""))
-        if last or not marked:
+            marked = [k for k in marked if s["layers"][k]["n_elem"] * factor <= max_elem]
+        nxt = refine_layers(s, marked, factor, max_elem) if marked else None
+        if nxt is not None and max_dof is not None and _n_dof(nxt) > max_dof:
+            marked, nxt = [], None
+        out.append(AdaptStep(s, n_dof, U, lay, marked, int(st.iters), rr, side, "z" if marked else ""))
+        if nxt is None:
             break
-        s = refine_layers(s, marked, factor, max_elem)
+        s = nxt
     return out
+
+
+def _n_dof(spec: dict) -> int:
+    """Unknowns of a mesh description: 3 (p + 1)^3 per element."""
+    cols = 5 * 4 ** spec["refine"] if spec["domain"] == "cylinder" else spec["nx"] * spec["ny"]
+    return 3 * cols * sum(l["n_elem"] for l in spec["layers"]) * (spec["p"] + 1) ** 3
