@@ -214,10 +214,25 @@ dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const 
 
 /* Elastic energy per layer, U_k = 1/2 sum over the elements of layer k of
  * int S_ij Y^ijkl S_kl dV with the unlifted strain S = D_(i u_j) and LGL
- * quadrature (Sec. 2.1).  u: device double; U_layers: host, n_layers values.
- * Synchronises the stream. */
-dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers,
+ * quadrature (Sec. 2.1: U = -1/2 int S_ij T^ij dV, split into the substrate
+ * and coating parts), and optionally the compliance form of the same energy,
+ * U_compl = 1/2 u . b with b the load vector of dgtn_rhs (the work of the
+ * applied pressure; for the solution of A u = b the two agree up to the
+ * discretisation error).  u: device double, n_dof values in the field layout;
+ * U_layers: host, n_layers values (J); U_compl: host, one value (J), or NULL
+ * to skip it.  Per-layer sums are taken on the device in a fixed order
+ * (deterministic).  Synchronises the stream; DGTN_ENAN if a result is not
+ * finite. */
+dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers, double* U_compl,
                         hipStream_t stream);
+
+/* Cubic constants of a material in Pa, out[0..2] = (c11, c12, c44): a cubic
+ * material's own (eq. constrel_cryst), or those of an isotropic one from its
+ * Young's modulus Y and Poisson ratio nu (eq. constrel_iso):
+ * lambda = Y nu / ((1 + nu)(1 - 2 nu)), mu = Y / (2 (1 + nu)),
+ * c11 = lambda + 2 mu, c12 = lambda, c44 = mu.  Pure host function;
+ * DGTN_EINVAL for a material that dgtn_create would reject. */
+dgtn_status dgtn_material_constants(const dgtn_material* material, double* out);
 
 /* Parameters of the energy gradient (the derivative of the layer energies of
  * Sec. 2.1 with respect to the materials of eqs. constrel_iso / constrel_cryst

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import DgtnError, check, load
 
 __all__ = ["Problem", "DgtnError", "noise_psd", "noise_psd_parts", "load", "problem_struct", "default_opts", "PARAM_KINDS",
-           "with_params", "param_value", "EnergyFn", "layer_energies"]
+           "with_params", "param_value", "material_constants", "EnergyFn", "layer_energies"]
 
 # Parameter kinds of the energy gradient (dgtn_param.kind)
 PARAM_KINDS = {"c11": 0, "c12": 1, "c44": 2, "youngs": 3, "poisson": 4, "thickness": 5,
@@ -30,12 +30,7 @@ def problem_struct(spec):
     """ctypes problem description from a spec dict (kept alive by the result)."""
     mats = (_lib.Material * len(spec["materials"]))()
     for i, m in enumerate(spec["materials"]):
-        if m["kind"] == "iso":
-            mats[i] = _lib.Material(0, m["Y"], m["nu"], 0.0, 0.0, 0.0)
-        elif m["kind"] == "cubic":
-            mats[i] = _lib.Material(1, 0.0, 0.0, m["c11"], m["c12"], m["c44"])
-        else:
-            raise ValueError(m["kind"])
+        mats[i] = _material_struct(m)
     lays = (_lib.Layer * len(spec["layers"]))()
     for i, l in enumerate(spec["layers"]):
         lays[i] = _lib.Layer(l["thickness"], l["n_elem"], l["ratio"], l["material"])
@@ -51,13 +46,21 @@ def problem_struct(spec):
     return p, (mats, lays)
 
 
-def _cubic_constants(m):
+def _material_struct(m):
+    if m["kind"] == "iso":
+        return _lib.Material(0, m["Y"], m["nu"], 0.0, 0.0, 0.0)
     if m["kind"] == "cubic":
-        return {k: m[k] for k in ("c11", "c12", "c44")}
-    Y, nu = m["Y"], m["nu"]
-    lam = Y * nu / ((1 + nu) * (1 - 2 * nu))
-    mu = Y / (2 * (1 + nu))
-    return {"c11": lam + 2 * mu, "c12": lam, "c44": mu}
+        return _lib.Material(1, 0.0, 0.0, m["c11"], m["c12"], m["c44"])
+    raise ValueError(m["kind"])
+
+
+def material_constants(m):
+    """Cubic constants {c11, c12, c44} (Pa) of a material dict, from the
+    library (dgtn_material_constants: an isotropic material's from its Young's
+    modulus and Poisson ratio)."""
+    out = (ctypes.c_double * 3)()
+    check(load().dgtn_material_constants(ctypes.byref(_material_struct(m)), out))
+    return {"c11": out[0], "c12": out[1], "c44": out[2]}
 
 
 def with_params(spec, params, values):
@@ -77,7 +80,7 @@ def with_params(spec, params, values):
         m = s["materials"][index]
         if kind in ("c11", "c12", "c44"):
             if m["kind"] != "cubic":
-                m = s["materials"][index] = {"kind": "cubic", **_cubic_constants(m)}
+                m = s["materials"][index] = {"kind": "cubic", **material_constants(m)}
             m[kind] = v
         elif kind in ("youngs", "poisson"):
             if m["kind"] != "iso":
@@ -96,7 +99,7 @@ def param_value(spec, kind, index):
         return float(spec["load"][kind])
     m = spec["materials"][index]
     if kind in ("c11", "c12", "c44"):
-        return float(m[kind] if m["kind"] == "cubic" else _cubic_constants(m)[kind])
+        return float(m[kind] if m["kind"] == "cubic" else material_constants(m)[kind])
     if kind in ("youngs", "poisson"):
         if m["kind"] != "iso":
             raise ValueError(f"material {index} is not isotropic")
@@ -244,15 +247,18 @@ class Problem:
         check(self.lib.dgtn_rhs(self.ctx, ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
-    def energy(self, u):
-        """Per-layer elastic energies (numpy, J)."""
+    def energy(self, u, compliance=False):
+        """Per-layer elastic energies (numpy, J); with compliance=True also
+        1/2 u . b, returned as (U_layers, U_compl)."""
         import torch
         self._ensure()
         self._check_field(u, torch.float64)
         out = np.zeros(self.n_layers)
+        comp = ctypes.c_double()
         check(self.lib.dgtn_energy(self.ctx, ctypes.c_void_p(u.data_ptr()),
-                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
-        return out
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(comp) if compliance else None, self._stream()))
+        return (out, comp.value) if compliance else out
 
     def jump_indicator(self, u, faces="all"):
         """Face-jump indicator of adaptive refinement: (eta_e^2 per element in the

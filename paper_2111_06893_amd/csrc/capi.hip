@@ -63,6 +63,44 @@ R* tau_of(const dgtn_ctx* c, const Level& L) {
 template double* tau_of<double>(const dgtn_ctx*, const Level&);
 template float* tau_of<float>(const dgtn_ctx*, const Level&);
 
+// First element of every layer on the finest level (layers occupy consecutive
+// z-elements, elements are numbered iz * n_cols + col), and the element count.
+std::vector<int> layer_first_elements(const dgtn_ctx* c) {
+    const Level& L = c->levels[0];
+    const int nl = (int)c->prob.layers.size();
+    std::vector<int> e0(nl + 1, L.E);
+    for (int iz = L.n_z - 1; iz >= 0; --iz) e0[L.zlayer[iz]] = iz * L.n_cols;
+    return e0;
+}
+
+// Layer energies and, if U_compl is given, the compliance 1/2 u . b, with the
+// per-element partial sums in ue / dot (E doubles each) and the per-layer sums
+// in sums (n_layers + 1 doubles): device buffers of the caller's choosing.
+// The results are copied to the host and the stream synchronised.
+dgtn_status energy_into(dgtn_ctx* c, const double* u, double* ue, double* dot, double* sums, double* U_layers,
+                        double* U_compl, hipStream_t s) {
+    const Level& L = c->levels[0];
+    const auto v = view_of<double>(c, L);
+    const auto& P = c->prob;
+    const int nl = (int)P.layers.size();
+    const int* lay_e0 = reinterpret_cast<const int*>(c->ws + c->off_lay);
+    hipError_t e = launch_energy(v, u, ue, s);
+    if (e == hipSuccess && U_compl)
+        e = launch_load_dot(v, reinterpret_cast<const double*>(c->ws + L.off_xy), P.F0, P.r0, P.xc, P.yc, u, dot, s);
+    if (e == hipSuccess) e = launch_layer_sums(ue, U_compl ? dot : nullptr, lay_e0, nl, c->y_ref, 0.5, sums, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(U_layers, sums, 8 * (size_t)nl, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && U_compl) e = hipMemcpyAsync(U_compl, sums + nl, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error(std::string("energy: ") + hipGetErrorString(e));
+        return DGTN_EHIP;
+    }
+    for (int k = 0; k < nl; ++k)
+        if (!std::isfinite(U_layers[k])) { set_error("non-finite energy"); return DGTN_ENAN; }
+    if (U_compl && !std::isfinite(*U_compl)) { set_error("non-finite compliance"); return DGTN_ENAN; }
+    return DGTN_OK;
+}
+
 // Workspace plan: geometry of every level (FP64 and FP32 mirrors), face
 // buffers, energy scratch, and the solver's vectors for `opts`.
 static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
@@ -87,6 +125,8 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
     }
     c->off_Ue = lay.take(8 * (size_t)c->levels[0].E);
     c->off_abc = lay.take(8 * 3 * (size_t)c->levels[0].E);
+    c->off_lay = lay.take(sizeof(int) * (c->prob.layers.size() + 1));
+    c->off_lsum = lay.take(8 * (c->prob.layers.size() + 1));
     plan_adjoint(c, lay);
     plan_solver(c, opts, lay);
 }
@@ -115,6 +155,14 @@ using namespace dgtn;
         }                                                                        \
     } while (0)
 
+// Positive definiteness of a material's stiffness (isotropic: Y > 0,
+// -1 < nu < 1/2; cubic: c44 > 0, c11 > |c12|, c11 + 2 c12 > 0).
+static bool material_ok(const dgtn_material& m) {
+    if (m.kind == DGTN_MAT_ISO) return m.youngs > 0 && m.poisson > -1.0 && m.poisson < 0.5;
+    if (m.kind == DGTN_MAT_CUBIC) return m.c44 > 0 && m.c11 > std::fabs(m.c12) && m.c11 + 2 * m.c12 > 0;
+    return false;
+}
+
 static dgtn_status validate(const dgtn_problem* p) {
     if (!p) { set_error("null problem"); return DGTN_EINVAL; }
     if (p->p < 1 || p->p > 7) { set_error("p must be in 1..7"); return DGTN_EINVAL; }
@@ -136,14 +184,11 @@ static dgtn_status validate(const dgtn_problem* p) {
             set_error("invalid layer " + std::to_string(i)); return DGTN_EINVAL;
         }
     }
-    for (int i = 0; i < p->n_materials; ++i) {
-        const auto& m = p->materials[i];
-        bool ok;
-        if (m.kind == DGTN_MAT_ISO) ok = m.youngs > 0 && m.poisson > -1.0 && m.poisson < 0.5;
-        else if (m.kind == DGTN_MAT_CUBIC) ok = m.c44 > 0 && m.c11 > std::fabs(m.c12) && m.c11 + 2 * m.c12 > 0;
-        else ok = false;
-        if (!ok) { set_error("material " + std::to_string(i) + " is not positive definite"); return DGTN_EINVAL; }
-    }
+    for (int i = 0; i < p->n_materials; ++i)
+        if (!material_ok(p->materials[i])) {
+            set_error("material " + std::to_string(i) + " is not positive definite");
+            return DGTN_EINVAL;
+        }
     const int bcs[3] = {p->bc_top, p->bc_bottom, p->bc_side};
     for (int b : bcs)
         if (b < DGTN_BC_DIRICHLET || b > DGTN_BC_FREE) { set_error("invalid boundary condition"); return DGTN_EINVAL; }
@@ -273,6 +318,7 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
             HIP_CHECK(puti(L.off_zmat, L.zmat));
             HIP_CHECK(put64(L.off_xy, L.xy));
         }
+        HIP_CHECK(puti(c->off_lay, layer_first_elements(c)));
         st = bind_adjoint(c, s);
         if (st != DGTN_OK) return st;
         st = bind_solver(c, s);
@@ -321,24 +367,20 @@ dgtn_status dgtn_rhs(dgtn_ctx* c, double* b, hipStream_t s) {
     return DGTN_OK;
 }
 
-dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, hipStream_t s) {
+dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, double* U_compl, hipStream_t s) {
     if (!c || !u || !U_layers) { set_error("null argument"); return DGTN_EINVAL; }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
-    const Level& L = c->levels[0];
-    auto v = view_of<double>(c, L);
-    double* Ue = reinterpret_cast<double*>(c->ws + c->off_Ue);
-    HIP_CHECK(launch_energy(v, u, Ue, s));
-    std::vector<double> h(L.E);
-    HIP_CHECK(hipMemcpyAsync(h.data(), Ue, 8 * (size_t)L.E, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    const int nl = (int)c->prob.layers.size();
-    for (int k = 0; k < nl; ++k) U_layers[k] = 0;
-    for (int e = 0; e < L.E; ++e) {  // fixed order: deterministic
-        const int iz = e / L.n_cols;
-        U_layers[L.zlayer[iz]] += h[e] * c->y_ref;
-    }
-    for (int k = 0; k < nl; ++k)
-        if (!std::isfinite(U_layers[k])) { set_error("non-finite energy"); return DGTN_ENAN; }
+    return energy_into(c, u, reinterpret_cast<double*>(c->ws + c->off_Ue), reinterpret_cast<double*>(c->ws + c->off_abc),
+                       reinterpret_cast<double*>(c->ws + c->off_lsum), U_layers, U_compl, s);
+}
+
+dgtn_status dgtn_material_constants(const dgtn_material* m, double* out) {
+    if (!m || !out) { set_error("null argument"); return DGTN_EINVAL; }
+    if (!material_ok(*m)) { set_error("material is not positive definite"); return DGTN_EINVAL; }
+    Problem P;
+    P.materials.assign(1, *m);
+    const std::vector<double> c = material_constants(P);
+    std::copy(c.begin(), c.end(), out);
     return DGTN_OK;
 }
 

@@ -38,6 +38,7 @@ struct dgtn_ctx {
     dgtn_solve_opts bound_opts{};
     bool has_opts = false;
     size_t off_Ue = 0, off_abc = 0;
+    size_t off_lay = 0, off_lsum = 0;  // per-layer first elements [n_layers + 1]; per-layer sums [n_layers + 1]
     dgtn::AdjointLayout adj;
     std::vector<std::vector<char>> staging;  // host staging of FP32 uploads
     dgtn::SolverState* solver = nullptr;
@@ -62,6 +63,10 @@ template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s);
 hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
                       int mode, double* b, hipStream_t s);
+hipError_t launch_load_dot(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
+                           const double* u, double* out, hipStream_t s);
+hipError_t launch_layer_sums(const double* v, const double* dot, const int* lay_e0, int n_layers, double scale,
+                             double dot_scale, double* sums, hipStream_t s);
 template <typename R>
 hipError_t launch_energy(const LevelView<R>& L, const double* u, R* Ue, hipStream_t s);
 hipError_t launch_energy_invariants(const LevelView<double>& L, const double* u, double* abc, hipStream_t s);

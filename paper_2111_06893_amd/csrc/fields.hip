@@ -11,23 +11,20 @@ namespace dgtn {
 
 namespace {
 
-// Load vector of the Gaussian pressure on DGTN_BC_PRESSURE faces:
-// b = -w_face J^Sigma n p(r), which is +z on the loaded face z = 0.
+// Load vector of the Gaussian pressure on DGTN_BC_PRESSURE faces at node
+// (i, j, k) of element e: b = -w_face J^Sigma n p(r), which is +z on the loaded
+// face z = 0, summed over the element faces the node lies on.
 // mode 0: p itself; 1, 2, 3: its derivative with respect to the beam width r0
 // and the beam centre xc, yc (the load vector's parameter derivatives).
 template <int N>
-__global__ __launch_bounds__(threads_for<N>()) void k_rhs(LevelView<double> L, const double* __restrict__ xy,
-                                                         double F0, double r0, double xc, double yc, int mode,
-                                                         double* __restrict__ b) {
-    constexpr int N2 = N * N, N3 = N2 * N;
-    const int e = blockIdx.x;
-    const int tid = threadIdx.x;
-    if (tid >= N3) return;
-    const int i = tid % N, j = (tid / N) % N, k = tid / N2;
+__device__ inline void load_at_node(const LevelView<double>& L, const double* __restrict__ xy, double F0, double r0,
+                                    double xc, double yc, int mode, int e, int i, int j, int k, double acc[3]) {
+    constexpr int N2 = N * N;
+    acc[0] = acc[1] = acc[2] = 0;
+    const bool fi = (i == 0) | (i == N - 1), fj = (j == 0) | (j == N - 1), fk = (k == 0) | (k == N - 1);
+    if (!(fi | fj | fk)) return;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const NodeGeo<double> g = node_geo<N>(L, col, iz, i, j);
-    double acc[3] = {0, 0, 0};
-    const bool fi = (i == 0) | (i == N - 1), fj = (j == 0) | (j == N - 1), fk = (k == 0) | (k == N - 1);
     const int faces[3] = {fi ? (i == 0 ? 0 : 1) : -1, fj ? (j == 0 ? 2 : 3) : -1, fk ? (k == 0 ? 4 : 5) : -1};
     const double x = xy[(size_t)col * 2 * N2 + j * N + i] - xc;
     const double y = xy[(size_t)col * 2 * N2 + N2 + j * N + i] - yc;
@@ -48,8 +45,72 @@ __global__ __launch_bounds__(threads_for<N>()) void k_rhs(LevelView<double> L, c
         else wsig = L.w[i] * L.w[k] * 0.5 * g.hz * g.det2 * amag;
         for (int c = 0; c < 3; ++c) acc[c] -= wsig * n[c] * p;
     }
+}
+
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_rhs(LevelView<double> L, const double* __restrict__ xy,
+                                                         double F0, double r0, double xc, double yc, int mode,
+                                                         double* __restrict__ b) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid >= N3) return;
+    double acc[3];
+    load_at_node<N>(L, xy, F0, r0, xc, yc, mode, e, tid % N, (tid / N) % N, tid / N2, acc);
     double* be = b + (size_t)e * 3 * N3;
     for (int c = 0; c < 3; ++c) be[c * N3 + tid] = acc[c];
+}
+
+// Per element, sum over its nodes of b . u with b the load vector (mode 0 of
+// load_at_node): the element's share of the compliance u . b, without storing b.
+template <int N>
+__global__ __launch_bounds__(threads_for<N>()) void k_load_dot(LevelView<double> L, const double* __restrict__ xy,
+                                                              double F0, double r0, double xc, double yc,
+                                                              const double* __restrict__ u, double* __restrict__ out) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = threads_for<N>();
+    __shared__ double red[NT / 64];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double d = 0;
+    if (tid < N3) {
+        double acc[3];
+        load_at_node<N>(L, xy, F0, r0, xc, yc, 0, e, tid % N, (tid / N) % N, tid / N2, acc);
+        const double* ue = u + (size_t)e * 3 * N3 + tid;
+        if (acc[0] != 0 || acc[1] != 0 || acc[2] != 0) d = acc[0] * ue[0] + acc[1] * ue[N3] + acc[2] * ue[2 * N3];
+    }
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);   // fixed order: deterministic
+    if (lane == 0) red[wave] = d;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        out[e] = t;
+    }
+}
+
+// Per-layer sums of per-element values in a fixed order (deterministic):
+// block k < n_layers sums v[lay_e0[k] .. lay_e0[k+1]) times `scale` into
+// sums[k]; block n_layers, when dot is given, sums dot[0 .. lay_e0[n_layers])
+// times `dot_scale` into sums[n_layers].
+constexpr int kSumThreads = 256;
+__global__ __launch_bounds__(kSumThreads) void k_layer_sums(const double* __restrict__ v, const double* __restrict__ dot,
+                                                           const int* __restrict__ lay_e0, int n_layers, double scale,
+                                                           double dot_scale, double* __restrict__ sums) {
+    __shared__ double red[kSumThreads];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const bool is_dot = k == n_layers;
+    const double* src = is_dot ? dot : v;
+    const int a = is_dot ? 0 : lay_e0[k], b = is_dot ? lay_e0[n_layers] : lay_e0[k + 1];
+    double t = 0;
+    for (int q = a + tid; q < b; q += kSumThreads) t += src[q];
+    red[tid] = t;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) sums[k] = red[0] * (is_dot ? dot_scale : scale);
 }
 
 // Per-element energy 1/2 sum_nodes w J D_(i u_j) Y D_(k u_l), in units of y_ref.
@@ -282,6 +343,22 @@ hipError_t launch_rhs(const LevelView<double>& L, const double* xy, double F0, d
         hipLaunchKernelGGL((k_rhs<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, xy, F0, r0, xc, yc, mode, b);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_load_dot(const LevelView<double>& L, const double* xy, double F0, double r0, double xc, double yc,
+                           const double* u, double* out, hipStream_t s) {
+    return dispatch_n(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_load_dot<NN>), dim3(L.E), dim3(threads_for<NN>()), 0, s, L, xy, F0, r0, xc, yc, u, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_layer_sums(const double* v, const double* dot, const int* lay_e0, int n_layers, double scale,
+                             double dot_scale, double* sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_layer_sums, dim3(n_layers + (dot ? 1 : 0)), dim3(kSumThreads), 0, s, v, dot, lay_e0, n_layers,
+                       scale, dot_scale, sums);
+    return hipGetLastError();
 }
 
 hipError_t launch_jump_indicator(const LevelView<double>& L, const double* u, int which, double* eta,

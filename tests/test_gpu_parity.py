@@ -102,9 +102,14 @@ def test_rhs_and_energy_match_oracle(name):
     bref = dg.rhs(O)
     assert np.abs(b - bref).max() <= 1e-13 * np.abs(bref).max()
     u = W.random_field(spec, seed=13) * 1e-9
-    U = P.energy(_dev(u))
+    U, comp = P.energy(_dev(u), compliance=True)
     Uref = dg.energy_layers(O, u)
     np.testing.assert_allclose(U, Uref, rtol=1e-12)
+    np.testing.assert_array_equal(P.energy(_dev(u)), U)        # the compliance output changes nothing else
+    # 1/2 u . b of a random field: a sum of terms of both signs, so the bar is relative to
+    # the sum of their magnitudes
+    cref = dg.compliance(O, u, bref)
+    assert abs(comp - cref) <= 1e-13 * 0.5 * float(np.sum(np.abs(u * bref))), (comp, cref)
 
 
 @pytest.mark.parametrize("name", ["config1", "cyl_refine0_p4_cubic", "box_p2_pressure_sides"])

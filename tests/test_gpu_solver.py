@@ -122,12 +122,15 @@ def test_vcycle_odd_coarse_size():
     _vcycle_check(spec, 2, 0.7, 243)
 
 
-def _solve_energy(spec, prec, floor_ok=False, **kw):
+def _solve_energy(spec, prec, floor_ok=False, compliance=False, **kw):
     P = dgtn.Problem(spec)
     opts = dgtn.default_opts(prec, **kw)
     u, st = P.solve(opts=opts, raise_on_noconv=not floor_ok)
     if floor_ok:   # stopped at the FP64 residual floor
         assert st.rel_res < 1e-9, st.rel_res
+    if compliance:
+        U, comp = P.energy(u, compliance=True)
+        return U, st, comp
     return P.energy(u), st
 
 
@@ -150,11 +153,14 @@ def _rtol(name):
 def test_fp64_solve_matches_oracle_energy(name):
     g = _golden(name)
     print(f"[solver] fp64 solve {name}", flush=True)
-    U, st = _solve_energy(g["spec"], 64, floor_ok=name.endswith("_dense"), rtol=_rtol(name), max_iter=8000)
+    U, st, comp = _solve_energy(g["spec"], 64, floor_ok=name.endswith("_dense"), compliance=True,
+                                rtol=_rtol(name), max_iter=8000)
     ref = np.array(g["U_layers"])
     tol = 5e-10 if name.endswith("_dense") else 1e-10
     assert abs(U.sum() / ref.sum() - 1) < tol
     np.testing.assert_allclose(U, ref, rtol=1e-9)
+    # the compliance form 1/2 u . b of the same solution against the oracle's
+    assert abs(comp / g["compliance"] - 1) < tol, (comp, g["compliance"])
 
 
 @pytest.mark.parametrize("name", GOLDEN_CASES)

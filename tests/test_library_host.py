@@ -62,6 +62,29 @@ def test_invalid_problems_are_rejected():
         dgtn.Problem(bad)
 
 
+@pytest.mark.parametrize("mat", [W.FUSED_SILICA, W.COATING_ISO, {"kind": "iso", "Y": 3.0e9, "nu": -0.4},
+                                 W.CRYSTAL_A])
+def test_material_constants_match_oracle_stiffness(mat):
+    # the library's constants (eq. constrel_iso for an isotropic material) against the
+    # entries of the oracle's full stiffness tensor: Y_xxxx = c11, Y_xxyy = c12, Y_xyxy = c44
+    from oracle import material
+    c = dgtn.material_constants(mat)
+    Y = material.tensor(mat)
+    ref = {"c11": Y[0, 0, 0, 0], "c12": Y[0, 0, 1, 1], "c44": Y[0, 1, 0, 1]}
+    for k in ref:
+        assert abs(c[k] / ref[k] - 1) < 1e-14, (k, c[k], ref[k])
+    assert dgtn.param_value(W.config4(), "c12", 1) == pytest.approx(dgtn.material_constants(W.COATING_ISO)["c12"])
+    s = dgtn.with_params(W.config4(), [("c44", 0)], [31e9])
+    assert s["materials"][0] == {"kind": "cubic", **dgtn.material_constants(W.FUSED_SILICA), "c44": 31e9}
+
+
+def test_material_constants_reject_invalid_materials():
+    for bad in ({"kind": "iso", "Y": 70e9, "nu": 0.5}, {"kind": "iso", "Y": -1.0, "nu": 0.2},
+                {"kind": "cubic", "c11": 50e9, "c12": 60e9, "c44": 30e9}):
+        with pytest.raises(dgtn.DgtnError, match="positive definite"):
+            dgtn.material_constants(bad)
+
+
 def test_noise_psd_matches_oracle_formula():
     U = [2.4e-11, 1.7e-13]
     phi = [1e-6, 4e-4]
