@@ -226,6 +226,21 @@ dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const 
 dgtn_status dgtn_energy(dgtn_ctx* ctx, const double* u, double* U_layers, double* U_compl,
                         hipStream_t stream);
 
+/* dgtn_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels, the same results bit for bit, but the per-element and
+ * per-layer partial sums live in a fixed device array of the library
+ * (2.03 MiB per device, held until the process ends) instead of the bound
+ * workspace.  Calls no hipMalloc / hipFree and no allocating library routine.
+ * Maximum: 131072 elements and 4096 layers (DGTN_EINVAL beyond, before any
+ * device work).  The workspace must still be bound (it holds the geometry) and
+ * the device it was bound on must be current.  Every call on one device
+ * shares that array, so calls that overlap on one device (other streams,
+ * other threads, other contexts) race and must be serialised by the caller.
+ * Arguments, outputs and errors as in dgtn_energy; synchronises the stream. */
+dgtn_status dgtn_energy_noalloc(dgtn_ctx* ctx, const double* u, double* U_layers, double* U_compl,
+                                hipStream_t stream);
+
 /* Cubic constants of a material in Pa, out[0..2] = (c11, c12, c44): a cubic
  * material's own (eq. constrel_cryst), or those of an isotropic one from its
  * Young's modulus Y and Poisson ratio nu (eq. constrel_iso):

@@ -62,6 +62,7 @@ _SIGS = {
     "dgtn_precondition": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, c_void_p]),
     "dgtn_energy": (c_int, [c_void_p, c_void_p, P(c_double), P(c_double), c_void_p]),
     "dgtn_material_constants": (c_int, [P(Material), P(c_double)]),
+    "dgtn_energy_noalloc": (c_int, [c_void_p, c_void_p, P(c_double), P(c_double), c_void_p]),
     "dgtn_energy_grad": (c_int, [c_void_p, c_void_p, P(c_double), c_void_p, c_void_p]),
     "dgtn_grad": (c_int, [c_void_p, c_void_p, c_void_p, P(c_double), c_int, P(Param), P(c_double), c_void_p]),
     "dgtn_noise_psd": (c_int, [P(c_double), P(c_double), c_int, c_double, c_double, c_double, P(c_double)]),

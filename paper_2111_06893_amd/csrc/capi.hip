@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -197,6 +198,35 @@ static dgtn_status validate(const dgtn_problem* p) {
     return DGTN_OK;
 }
 
+// Device scratch of dgtn_energy_noalloc, for callers that cannot allocate device
+// memory: per-element energies [kNoallocElems], per-element load products
+// [kNoallocElems] and per-layer sums [kNoallocLayers + 1] (2.03 MiB per device,
+// held until the process ends).  Host code never uses the array's name as an
+// address: the device address is resolved once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+static constexpr int kNoallocElems = 1 << 17;
+static constexpr int kNoallocLayers = 4096;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * (size_t)kNoallocElems + kNoallocLayers + 1];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, resolved on the first call there.
+static dgtn_status scratch_for_current_device(double** out) {
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) { set_error("device index out of range"); return DGTN_EINVAL; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) { set_error("no device address for the scratch array"); return DGTN_EHIP; }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return DGTN_OK;
+}
+
 extern "C" {
 
 dgtn_status dgtn_create(const dgtn_problem* p, dgtn_ctx** out) {
@@ -372,6 +402,25 @@ dgtn_status dgtn_energy(dgtn_ctx* c, const double* u, double* U_layers, double* 
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     return energy_into(c, u, reinterpret_cast<double*>(c->ws + c->off_Ue), reinterpret_cast<double*>(c->ws + c->off_abc),
                        reinterpret_cast<double*>(c->ws + c->off_lsum), U_layers, U_compl, s);
+}
+
+dgtn_status dgtn_energy_noalloc(dgtn_ctx* c, const double* u, double* U_layers, double* U_compl, hipStream_t s) {
+    if (!c || !u || !U_layers) { set_error("null argument"); return DGTN_EINVAL; }
+    const Level& L = c->levels[0];
+    if (L.E > kNoallocElems) {
+        set_error("dgtn_energy_noalloc: " + std::to_string(L.E) + " elements exceed its maximum of " +
+                  std::to_string(kNoallocElems));
+        return DGTN_EINVAL;
+    }
+    if ((int)c->prob.layers.size() > kNoallocLayers) {
+        set_error("dgtn_energy_noalloc: more than " + std::to_string(kNoallocLayers) + " layers");
+        return DGTN_EINVAL;
+    }
+    if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
+    double* sp = nullptr;
+    const dgtn_status st = scratch_for_current_device(&sp);
+    if (st != DGTN_OK) return st;
+    return energy_into(c, u, sp, sp + kNoallocElems, sp + 2 * (size_t)kNoallocElems, U_layers, U_compl, s);
 }
 
 dgtn_status dgtn_material_constants(const dgtn_material* m, double* out) {
