@@ -20,7 +20,7 @@ from oracle import dg, solve  # noqa: E402
 
 def cases():
     out = {"config1": W.config1()}
-    for s in range(3):
+    for s in range(10):
         out[f"config3_seed{s}"] = W.config3(seed=s)
     # thin-coating cases small enough for a dense direct solve (the block-Jacobi CG of the
     # oracle converges too slowly on 1e-3 coatings)
