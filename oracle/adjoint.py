@@ -84,10 +84,11 @@ def solve_state(spec, dense=True, w_layers=None):
     P = dg.Problem(spec)
     b = dg.rhs(P)
     if dense:
-        A = dg.assemble_dense(P)
-        u = np.linalg.solve(A, b.ravel()).reshape(P.shape)
+        # A is symmetric (weak form), so the factorisation serves the adjoint system too
+        F = solve.RefinedDense(P)
+        u = F.solve(b)[0].reshape(P.shape)
         g = energy_grad_u(P, u, w_layers)
-        lam = np.linalg.solve(A.T, g.ravel()).reshape(P.shape)
+        lam = F.solve(g)[0].reshape(P.shape)
     else:
         u = solve.pcg(P, b, rtol=1e-13)[0]
         g = energy_grad_u(P, u, w_layers)
@@ -96,11 +97,16 @@ def solve_state(spec, dense=True, w_layers=None):
 
 
 def functional(spec, u, lam, w_layers=None):
-    """1/2 u^T K_w u - lambda^T A u + lambda^T b for fixed u, lambda under `spec`."""
+    """1/2 u^T K_w u - lambda^T A u + lambda^T b for fixed u, lambda under `spec`,
+    in extended precision (numpy longdouble): lambda^T A u and lambda^T b are
+    large and nearly cancel (the interior-penalty terms of a thin layer), and
+    gradient() divides differences of this value by a small step."""
     P = dg.Problem(spec)
-    U = dg.energy_layers(P, u)
+    ul = np.asarray(u, dtype=np.longdouble)
+    ll = np.asarray(lam, dtype=np.longdouble)
+    U = dg.energy_layers(P, ul)
     w = np.ones(len(U)) if w_layers is None else np.asarray(w_layers, float)
-    return float(np.dot(w, U)) - float(np.sum(lam * dg.apply(P, u))) + float(np.sum(lam * dg.rhs(P)))
+    return np.sum(w.astype(np.longdouble) * U) - np.sum(ll * dg.apply(P, ul)) + np.sum(ll * dg.rhs(P))
 
 
 def param_step(spec, kind, index, rel_step):
@@ -121,5 +127,5 @@ def gradient(spec, params, w_layers=None, rel_step=1e-3, dense=True):
         t0 = get_param(spec, kind, index)
         h = param_step(spec, kind, index, rel_step)
         f = [functional(set_param(spec, kind, index, t0 + s * h), u, lam, w_layers) for s in (-2, -1, 1, 2)]
-        out.append((f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h))
+        out.append(float((f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * np.longdouble(h))))
     return J, np.array(out)

@@ -101,7 +101,7 @@ def _neighbour_face(prob, arr, f):
     allf = np.stack([get_face(arr, g, N) for g in range(6)], axis=1)   # [E, 6, A..., NN]
     nb = m.nbr[:, f]
     ok = nb >= 0
-    out = np.zeros(allf.shape[:1] + allf.shape[2:])
+    out = np.zeros(allf.shape[:1] + allf.shape[2:], dtype=allf.dtype)
     src = allf[nb[ok], m.nbr_face[ok, f]]                              # [E', A..., NN]
     idx = m.perm[ok, f]
     idx = idx.reshape((idx.shape[0],) + (1,) * (src.ndim - 2) + (idx.shape[1],))
@@ -192,7 +192,7 @@ def residual(prob, u, data=None, form="weak", couple=True):
         add_face(S, f, N, dS)
     T = contract(Y, S)                          # [E, i, j, ...]
     if form == "weak":
-        r = np.zeros(prob.shape)
+        r = np.zeros(prob.shape, dtype=T.dtype)
         for mdir in range(3):
             Fm = wJ[:, None] * np.einsum("ei...,eij...->ej...", geo.inv[:, mdir], T)
             r += ref_deriv_T(Fm, geo.D, mdir)
@@ -200,7 +200,7 @@ def residual(prob, u, data=None, form="weak", couple=True):
             ws = geo.wface[f][None] * geo.jsig[:, f]
             add_face(r, f, N, -ws[:, None, :] * fluxes[f])
     elif form == "strong":
-        divT = np.zeros(prob.shape)
+        divT = np.zeros(prob.shape, dtype=T.dtype)
         for mdir in range(3):
             dT = ref_deriv(T, geo.D, mdir)                 # [E, i, j, ...]
             divT += np.einsum("ei...,eij...->ej...", geo.inv[:, mdir], dT)
@@ -230,7 +230,8 @@ def _neighbour_h(prob, f):
 
 
 def apply(prob, u, form="weak", couple=True):
-    """A u."""
+    """A u, in the floating-point type of u (float64, or numpy's extended
+    longdouble for the residuals of iterative refinement)."""
     return residual(prob, u, HOMOGENEOUS, form=form, couple=couple)
 
 
@@ -246,7 +247,7 @@ def energy_layers(prob, u):
     dens = np.einsum("eij...,eijkl,ekl...->e...", Su, prob.Yel, Su)
     wJ = prob.geo.w3[None] * prob.geo.det
     per_el = 0.5 * np.sum(wJ * dens, axis=(1, 2, 3))
-    out = np.zeros(prob.mesh.n_layers)
+    out = np.zeros(prob.mesh.n_layers, dtype=per_el.dtype)
     np.add.at(out, prob.mesh.layer, per_el)
     return out
 

@@ -42,22 +42,13 @@ def run(name, spec):
     P = dg.Problem(spec)
     b = dg.rhs(P)
     if name.endswith("_dense"):
-        # dense LU, then iterative refinement with the residual in extended precision, so
-        # that the solution is accurate to rounding rather than to cond(A) * eps
-        import scipy.linalg as sla
-        A = dg.assemble_dense(P)
-        bf = b.ravel()
-        lu = sla.lu_factor(A)
-        u = sla.lu_solve(lu, bf)
-        Al, bl = A.astype(np.longdouble), bf.astype(np.longdouble)
-        for it in range(1, 6):
-            r = bl - Al @ u.astype(np.longdouble)
-            d = sla.lu_solve(lu, r.astype(np.float64))
-            u = (u.astype(np.longdouble) + d.astype(np.longdouble)).astype(np.float64)
-            if np.linalg.norm(d) <= 1e-16 * np.linalg.norm(u):
-                break
-        rel = float(np.linalg.norm((bl - Al @ u.astype(np.longdouble)).astype(np.float64)) / np.linalg.norm(bf))
+        # dense LU of the assembled matrix refined with the operator's own residual in
+        # extended precision (oracle.solve.RefinedDense): the operator's solution to
+        # the rounding of u, not that of the matrix's rounded entries
+        F = solve.RefinedDense(P)
+        u, rel = F.solve(b)
         u = u.reshape(P.shape)
+        it = 0
     else:
         u, it, rel = solve.pcg(P, b, rtol=1e-13, maxit=60000)
     U = dg.energy_layers(P, u)
