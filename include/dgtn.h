@@ -129,6 +129,8 @@ typedef struct {
     int smoother;             /* Schwarz subdomains: DGTN_SMOOTH_ELEMENT or DGTN_SMOOTH_COLUMN */
     int krylov;               /* DGTN_KRYLOV_FGMRES or DGTN_KRYLOV_FCG          */
     int overlap;              /* column-subdomain overlap in node lines (0..3)  */
+    int residual_precision;   /* true residual b - A u: 64 (or 0) FP64, 128
+                                 double-double (dgtn_residual; p <= 6)          */
 } dgtn_solve_opts;
 
 /* Additive-Schwarz subdomains: one element, or one whole z-column of elements
@@ -199,6 +201,18 @@ dgtn_status dgtn_rhs(dgtn_ctx* ctx, double* b, hipStream_t stream);
  * iterate.  DGTN_ENAN on a NaN/Inf. */
 dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* b,
                        double* u, dgtn_solve_stats* stats, hipStream_t stream);
+
+/* r = b - A u with A u evaluated in double-double arithmetic (about 106
+ * significant bits) over the same double coefficient tables as dgtn_apply, and
+ * r rounded to double once: the extended-precision residual of iterative
+ * refinement in three precisions (Sec. 2.3, eq. matrix_eqn).  It tells rounding
+ * in the evaluation of A u apart from the rounding of u itself: where the two
+ * residuals agree, a solve that stagnates has reached the attainable accuracy
+ * of a double u (eps |A| |u|, large on thin layers through the interior-penalty
+ * terms of eq. penalty).  dgtn_solve uses it for its true residual when
+ * opts->residual_precision is 128.  b, u, r: device double, n_dof values; r
+ * must not alias u.  Available for p <= 6 (DGTN_EINVAL otherwise). */
+dgtn_status dgtn_residual(dgtn_ctx* ctx, const double* b, const double* u, double* r, hipStream_t stream);
 
 /* z = M^{-1} v: one application of the solver's preconditioner (the V-cycle
  * of dgtn_solve with the same options, in opts->precond_precision), for the

@@ -123,7 +123,8 @@ def noise_psd_parts(U_parts, phi_parts, T, f, F0):
 
 def default_opts(precision=64, **kw):
     o = dict(precond_precision=precision, restart=30, max_iter=20000, rtol=1e-11,
-             mg_levels=16, smooth_steps=1, smooth_damping=0.65, smoother=1, krylov=1, overlap=1)
+             mg_levels=16, smooth_steps=1, smooth_damping=0.65, smoother=1, krylov=1, overlap=1,
+             residual_precision=64)
     o.update(kw)
     return _lib.SolveOpts(**o)
 
@@ -236,6 +237,22 @@ class Problem:
         self._check_field(out, u.dtype)
         check(self.lib.dgtn_apply_stage(self.ctx, prec, stage, ctypes.c_void_p(u.data_ptr()),
                                         ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def residual(self, u, b=None, out=None):
+        """b - A u (b defaults to the load vector), with A u evaluated in
+        double-double arithmetic and rounded once (dgtn_residual)."""
+        import torch
+        self._ensure()
+        if b is None:
+            b = self.rhs()
+        self._check_field(u, torch.float64)
+        self._check_field(b, torch.float64)
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_field(out, torch.float64)
+        check(self.lib.dgtn_residual(self.ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
     def rhs(self, out=None):

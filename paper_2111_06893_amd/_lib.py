@@ -38,7 +38,7 @@ class Info(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precond_precision", c_int), ("restart", c_int), ("max_iter", c_int), ("rtol", c_double),
                 ("mg_levels", c_int), ("smooth_steps", c_int), ("smooth_damping", c_double),
-                ("smoother", c_int), ("krylov", c_int), ("overlap", c_int)]
+                ("smoother", c_int), ("krylov", c_int), ("overlap", c_int), ("residual_precision", c_int)]
 
 
 class Param(ctypes.Structure):
@@ -58,6 +58,7 @@ _SIGS = {
     "dgtn_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "dgtn_apply_stage": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "dgtn_rhs": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "dgtn_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dgtn_solve": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, P(SolveStats), c_void_p]),
     "dgtn_precondition": (c_int, [c_void_p, P(SolveOpts), c_void_p, c_void_p, c_void_p]),
     "dgtn_energy": (c_int, [c_void_p, c_void_p, P(c_double), P(c_double), c_void_p]),

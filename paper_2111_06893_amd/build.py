@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgtn.so")
-SOURCES = ["host.cpp", "kernels.hip", "fields.hip", "capi.hip", "solver.hip", "mg.hip", "adjoint.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "fields.hip", "capi.hip", "solver.hip", "mg.hip", "adjoint.hip", "residual.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -129,6 +129,7 @@ static void plan_layout(dgtn_ctx* c, const dgtn_solve_opts* opts, Layout& lay) {
     c->off_lay = lay.take(sizeof(int) * (c->prob.layers.size() + 1));
     c->off_lsum = lay.take(8 * (c->prob.layers.size() + 1));
     plan_adjoint(c, lay);
+    plan_residual(c, lay);
     plan_solver(c, opts, lay);
 }
 
@@ -350,6 +351,8 @@ dgtn_status dgtn_bind(dgtn_ctx* c, void* ws, size_t bytes, const dgtn_solve_opts
         }
         HIP_CHECK(puti(c->off_lay, layer_first_elements(c)));
         st = bind_adjoint(c, s);
+        if (st != DGTN_OK) return st;
+        st = bind_residual(c, s);
         if (st != DGTN_OK) return st;
         st = bind_solver(c, s);
         if (st != DGTN_OK) return st;

@@ -5,6 +5,7 @@
 
 #include <vector>
 
+#include "ddouble.h"
 #include "dual.h"
 #include "internal.h"
 
@@ -16,6 +17,13 @@ struct AdjointLayout {
     size_t wz = 0, u = 0, Au = 0, tau = 0, geo2 = 0, sig = 0, fnrm = 0, hz = 0, mat = 0, D = 0, w = 0, Ue = 0;
     size_t partial = 0, dots = 0;
     int nblk = 0;
+};
+
+// Workspace offsets of the double-double copies of the finest level's
+// coefficient tables (the extended-precision residual).
+struct ResidualLayout {
+    bool ok = false;  // available (the 16-byte kernels cover N <= 7)
+    size_t geo2 = 0, sig = 0, fnrm = 0, hz = 0, mat = 0, D = 0, w = 0;
 };
 
 struct Layout {
@@ -40,6 +48,7 @@ struct dgtn_ctx {
     size_t off_Ue = 0, off_abc = 0;
     size_t off_lay = 0, off_lsum = 0;  // per-layer first elements [n_layers + 1]; per-layer sums [n_layers + 1]
     dgtn::AdjointLayout adj;
+    dgtn::ResidualLayout res;
     std::vector<std::vector<char>> staging;  // host staging of FP32 uploads
     dgtn::SolverState* solver = nullptr;
     ~dgtn_ctx();
@@ -81,6 +90,15 @@ hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dua
                               hipStream_t s);
 template <>
 hipError_t launch_energy<Dual>(const LevelView<Dual>& L, const double* u, Dual* Ue, hipStream_t s);
+template <>
+hipError_t launch_traction<DD>(const LevelView<DD>& L, const DD* u, DD* tau, hipStream_t s);
+template <>
+hipError_t launch_apply<DD>(const LevelView<DD>& L, const DD* u, const DD* tau, DD* out, DD scale, hipStream_t s);
+
+// residual.hip
+void plan_residual(dgtn_ctx* c, Layout& lay);
+dgtn_status bind_residual(dgtn_ctx* c, hipStream_t s);
+hipError_t residual_dd(dgtn_ctx* c, const double* b, const double* u, double* r, hipStream_t s);
 
 // adjoint.hip
 void plan_adjoint(dgtn_ctx* c, Layout& lay);

@@ -6,14 +6,16 @@
 // the sum-factorised LGL contractions, reading each input once from LDS with
 // the 1D matrix D in scalar registers; node lanes (one per LGL node) do the
 // pointwise metric, lift and constitutive work; face lanes (one per face node)
-// do the jumps and numerical fluxes.  FP64, FP32 and the dual numbers of the
-// adjoint are the same template.
+// do the jumps and numerical fluxes.  FP64, FP32, the dual numbers of the
+// adjoint and the double-double numbers of the extended-precision residual are
+// the same template.
 //
 // The operator is applied in two passes:
 //   k_traction  t = n . Y . D u on the 6 N^2 face nodes of every element (the
 //               unlifted derivative entering the flux of eq. numflux);
 //   k_apply     lifted strain, stress, weak divergence and face fluxes, which
 //               read the neighbours' displacement traces and tractions.
+#include "ddouble.h"
 #include "element.h"
 
 namespace dgtn {
@@ -72,6 +74,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
 // the LDS at 40.5 KB.
 template <int N, typename R>
 constexpr int apply_waves() {
+    if constexpr (sizeof(R) == 16) return 4;  // dual and double-double numbers: 128 registers
     return (sizeof(R) == 8 && (N == 2 || N == 5 || N == 6)) ? 7 : 8;
 }
 
@@ -111,9 +114,10 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     // node role
     const bool nact = tid < N3;
     const int i = tid % N, j = (tid / N) % N, k = tid / N2;
-    // node metric: held in registers in FP32; in FP64, where registers bound the
-    // occupancy, loaded again (from cache) by the two phases that use it
-    constexpr bool kReloadGeo = sizeof(R) == 8;
+    // node metric: held in registers in FP32; in FP64 and the 16-byte types, where
+    // registers bound the occupancy, loaded again (from cache) by the two phases
+    // that use it
+    constexpr bool kReloadGeo = sizeof(R) >= 8;
     NodeGeo<R> g_held{1, 0, 0, 1, 1, 1};
     if constexpr (!kReloadGeo) {
         if (nact) g_held = node_geo<N>(L, col, iz, i, j);
@@ -331,6 +335,24 @@ hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dua
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
+        return hipGetLastError();
+    });
+}
+
+template <>
+hipError_t launch_traction<DD>(const LevelView<DD>& L, const DD* u, DD* tau, hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_traction<NN, DD>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
+        return hipGetLastError();
+    });
+}
+
+template <>
+hipError_t launch_apply<DD>(const LevelView<DD>& L, const DD* u, const DD* tau, DD* out, DD scale, hipStream_t s) {
+    return dispatch_dual(L.N, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        hipLaunchKernelGGL((k_apply<NN, DD>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }

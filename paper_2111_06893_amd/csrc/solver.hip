@@ -1,9 +1,10 @@
 // Krylov solve of A u = b (Sec. 2.3, eq. matrix_eqn).
 //
 // Restarted flexible GMRES in FP64 (the paper's GMRES; flexible so that the
-// preconditioner may vary, e.g. run in FP32).  Each restart recomputes the
-// true residual b - A u in FP64, which is iterative refinement when the
-// preconditioner is single precision.
+// preconditioner may vary, e.g. run in FP32), or flexible CG.  The true
+// residual b - A u is recomputed at restarts, every 50 CG iterations and at
+// convergence, in FP64 or, on request, in double-double arithmetic
+// (residual.hip): iterative refinement in two or three precisions.
 //
 // Preconditioner: a multigrid V-cycle (Sec. 2.3) on a hierarchy that first
 // lowers the polynomial degree (p -> p/2 -> ... -> 1) on the same mesh, then
@@ -1355,6 +1356,12 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     if (!(opts->rtol > 0) || opts->max_iter < 1 || opts->smooth_steps < 1 || !(opts->smooth_damping > 0)) {
         set_error("invalid solve options"); return DGTN_EINVAL;
     }
+    if (opts->residual_precision != 0 && opts->residual_precision != 64 && opts->residual_precision != 128) {
+        set_error("residual_precision must be 64 or 128"); return DGTN_EINVAL;
+    }
+    if (opts->residual_precision == 128 && !c->res.ok) {
+        set_error("the double-double residual covers p <= 6"); return DGTN_EINVAL;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     const bool verbose = std::getenv("DGTN_VERBOSE") != nullptr;
     SolverState& S = *c->solver;
@@ -1373,10 +1380,21 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     if ((st = dots(c, nullptr, 0, b, n, d, s)) != DGTN_OK) return st;
     const double bnorm = std::sqrt(d[0]);
     if (!std::isfinite(bnorm)) { set_error("non-finite right-hand side"); return DGTN_ENAN; }
-    auto true_residual = [&](double& beta) -> dgtn_status {
-        dgtn_status e = level_apply<double>(c, 0, u, r, yr, s);
+    // b - A u into `out`, in FP64 or (residual_precision 128) double-double
+    const bool dd_resid = opts->residual_precision == 128;
+    auto residual_into = [&](double* out) -> dgtn_status {
+        if (dd_resid) {
+            SHIP(residual_dd(c, b, u, out, s));
+            return DGTN_OK;
+        }
+        dgtn_status e = level_apply<double>(c, 0, u, out, yr, s);
         if (e != DGTN_OK) return e;
-        SHIP(vec_resid<double>(b, r, n, s));
+        SHIP(vec_resid<double>(b, out, n, s));
+        return DGTN_OK;
+    };
+    auto true_residual = [&](double& beta) -> dgtn_status {
+        dgtn_status e = residual_into(r);
+        if (e != DGTN_OK) return e;
         e = dots(c, nullptr, 0, r, n, d, s);
         if (e != DGTN_OK) return e;
         beta = std::sqrt(d[0]);
@@ -1439,8 +1457,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
             const int it = iters++;
             const bool replace = iters % refresh == 0;
             if (replace) {  // residual replacement
-                if ((st = level_apply<double>(c, 0, u, pr, yr, s)) != DGTN_OK) return st;
-                SHIP(vec_resid<double>(b, pr, n, s));
+                if ((st = residual_into(pr)) != DGTN_OK) return st;
                 ++restarts;
             }
             if (b32) {
@@ -1482,7 +1499,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
                 if (beta <= target) break;
                 char msg[128];
                 std::snprintf(msg, sizeof msg, "stagnated at relative residual %.3e (the attainable accuracy of "
-                              "the FP64 operator)", beta / bnorm);
+                              "the operator's arithmetic)", beta / bnorm);
                 why = msg;
                 result = DGTN_ENOCONV;
                 break;

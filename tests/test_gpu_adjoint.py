@@ -193,3 +193,80 @@ def test_grad_rejects_bad_parameters():
         P.grad(u, u, [("thickness", 5)])
     with pytest.raises(ValueError):
         P.grad(u, u, [("density", 0)])
+
+
+# --- the coated cylinder of 40 elements (coating 1e-3 R) -------------------------------
+# The oracle's gradients on this topology at p = 3 (tests/golden/make_gradients.py: dense
+# solves refined with extended-precision residuals, five-point differences of its own
+# operator).  The moduli enter A and K linearly, so the oracle's difference quotient is
+# exact up to rounding (1e-10); the Poisson ratios and the thickness enter nonlinearly and
+# its five-point step of 1e-3 relative leaves an O(1e-12) truncation and ~1e-10 of rounding
+# amplified by the step (1e-9).
+
+def _golden_gradients():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gradients.json")))
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_coated_cylinder_gradient_matches_oracle(case, prec):
+    g = _golden_gradients()
+    spec, params = g["spec"], [tuple(p) for p in g["params"]]
+    c = g["cases"][case]
+    w = np.array(c["w_layers"])
+    print(f"[adjoint] coated cylinder p=3 against the oracle, w={w.tolist()}, fp{prec} preconditioner", flush=True)
+    P = dgtn.Problem(spec)
+    # rtol below the attainable residual of a double-rounded solution: the solves end on
+    # stagnation there, with u refined by the double-double residual
+    o = dgtn.default_opts(prec, rtol=1e-14, max_iter=20000)
+    u, st = P.solve(opts=o, raise_on_noconv=False)
+    assert st.rel_res < 1e-9
+    J = float(np.dot(w, P.energy(u)))
+    lam, st2 = P.solve(b=P.energy_grad(u, w), opts=o, raise_on_noconv=False)
+    assert st2.rel_res < 1e-9
+    dJ = P.grad(u, lam, params, w)
+    print(f"J {J:.15e} vs {c['J']:.15e}; solves {st.iters}/{st2.iters} it, rel.res {st.rel_res:.1e}", flush=True)
+    tol_J = 1e-10 if prec == 64 else 1e-8
+    assert abs(J / c["J"] - 1) < tol_J
+    # per-layer gradients of the oracle (case 1 weighs the coating only): an entry of a
+    # weighted sum can cancel between the layers (dU/dd: +5.05e-11 coating, -5.37e-11
+    # substrate), so each entry is held relative to the sum of its layer parts' magnitudes
+    g_coat = np.array(g["cases"][1]["dJ"])
+    g_sub = np.array(g["cases"][0]["dJ"]) - g_coat
+    scale = np.abs(w[0] * g_coat) + np.abs(w[1] * g_sub)
+    for q, ((kind, index), a, b) in enumerate(zip(params, dJ, c["dJ"])):
+        if scale[q] < 1e-12 * scale.max():
+            continue                             # a structurally ~zero entry (Y with w = 0 on its layer)
+        tol = (1e-10 if kind == "youngs" else 1e-9) if prec == 64 else 1e-8
+        print(f"  {kind}[{index}] {a:.12e} oracle {b:.12e} rel {a / b - 1:+.2e} "
+              f"(of the layer parts {(a - b) / scale[q]:+.2e})", flush=True)
+        assert abs(a - b) < tol * scale[q], (kind, index, a, b)
+
+
+def test_coated_cylinder_gradient_central_differences():
+    # the benchmark's coated cylinder at p = 5 (coating 1e-3 R): central differences of the
+    # whole solve-and-energy pipeline with a relative step of 1e-6 against the adjoint; the
+    # difference quotient carries ~1e-8 of solve rounding amplified by the step
+    spec = W.config4()
+    w = np.array([1.0, 1.0])
+    params = COATING_PARAMS
+    print("[adjoint] coated cylinder p=5, central differences h = 1e-6", flush=True)
+    o = opts(1e-14)        # ends on stagnation at the rounding floor of the stored solution
+    P = dgtn.Problem(spec)
+    u, _ = P.solve(opts=o, raise_on_noconv=False)
+    lam, _ = P.solve(b=P.energy_grad(u, w), opts=o, raise_on_noconv=False)
+    dJ = P.grad(u, lam, params, w)
+    for (kind, index), a in zip(params, dJ):
+        t0 = dgtn.param_value(spec, kind, index)
+        h = 1e-6 * abs(t0)
+        f = []
+        for s in (-1, 1):
+            Q = dgtn.Problem(dgtn.with_params(spec, [(kind, index)], [t0 + s * h]))
+            uq, _ = Q.solve(opts=o, raise_on_noconv=False)
+            f.append(float(np.dot(w, Q.energy(uq))))
+            Q.close()
+        fd = (f[1] - f[0]) / (2 * h)
+        print(f"  {kind}[{index}] adjoint {a:.10e} central {fd:.10e} rel {a / fd - 1:+.2e}", flush=True)
+        assert abs(a / fd - 1) < 1e-6, (kind, index, a, fd)
