@@ -277,6 +277,17 @@ constexpr int line_threads() {
     return ((m + 127) / 128) * 128;
 }
 
+// Lanes of the two operator kernels (k_traction, k_apply).  At N = 6 the node
+// and face phases have 216 tasks and the line phases 324: 256 lanes, whose
+// line phases take a second pass over the 68 remaining lines, let six
+// workgroups share a CU (their LDS allows it) where 384 lanes allowed four
+// within the same number of waves, so more elements hide each other's
+// latencies.  Elsewhere one lane per task of the largest phase.
+template <int N>
+constexpr int op_threads() {
+    return N == 6 ? 256 : line_threads<N>();
+}
+
 // Line task t < 9 N^2: direction d (xi, eta, zeta), component c, and the offset
 // and stride of the line's N nodes within one component's N^3 block.
 template <int N>
@@ -315,12 +326,14 @@ __device__ __forceinline__ void line_contract(const LevelView<R>& L, const R* sr
 
 // Reference derivatives of the three components along the three directions,
 // sG[(d * 3 + c) * N^3 + node], from the LDS copy of u.
-template <int N, typename R>
+// NT lanes take the 9 N^2 lines in passes of NT.
+template <int N, typename R, int NT = line_threads<N>()>
 __device__ __forceinline__ void ref_derivatives(const LevelView<R>& L, const R* su, R* sG, int tid) {
     constexpr int N3 = N * N * N;
-    if (tid < 9 * N * N) {
+#pragma unroll
+    for (int t = tid; t < 9 * N * N; t += NT) {
         int d, c, base, stride;
-        line_of<N>(tid, d, c, base, stride);
+        line_of<N>(t, d, c, base, stride);
         R* dst = sG + (d * 3 + c) * N3 + base;
         line_contract<N, false>(L, su + c * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
     }

@@ -23,9 +23,9 @@ namespace dgtn {
 namespace {
 
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
-                                                               R* __restrict__ tau) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+__global__ __launch_bounds__(op_threads<N>()) void k_traction(LevelView<R> L, const R* __restrict__ u,
+                                                             R* __restrict__ tau) {
+    constexpr int N2 = N * N, N3 = N2 * N, NT = op_threads<N>();
     __shared__ R su[3 * N3];
     __shared__ R sG[9 * N3];
     __shared__ R sown[5];
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     // waves 1.. stage u while wave 0 reads the element's material (two dependent
     // table reads), so that the two latencies overlap instead of adding up
     if (tid >= 64) {
-        stage_to_lds<3 * N3, line_threads<N>() - 64>(su, ue, tid - 64);
+        stage_to_lds<3 * N3, NT - 64>(su, ue, tid - 64);
     } else if (tid == 0) {
         const int m = L.zmat[iz];
         sown[0] = L.mat[3 * m];
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
     if (act) face_node<N>(f, fi, i, j, k);
     NodeGeo<R> g = act ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
     __syncthreads();
-    ref_derivatives<N>(L, su, sG, tid);
+    ref_derivatives<N, R, NT>(L, su, sG, tid);
     __syncthreads();
     if (!act) return;
     R G[3][3], S[6], T[6], n[3], amag, t[3];
@@ -75,14 +75,16 @@ __global__ __launch_bounds__(line_threads<N>()) void k_traction(LevelView<R> L, 
 template <int N, typename R>
 constexpr int apply_waves() {
     if constexpr (sizeof(R) == 16) return 4;  // dual and double-double numbers: 128 registers
-    return (sizeof(R) == 8 && (N == 2 || N == 5 || N == 6)) ? 7 : 8;
+    if constexpr (sizeof(R) == 8 && N == 6) return 6;  // six workgroups of four waves per CU
+    return (sizeof(R) == 8 && (N == 2 || N == 5)) ? 7 : 8;
 }
 
 template <int N, typename R>
-__global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_apply(LevelView<R> L, const R* __restrict__ u,
+__global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_apply(LevelView<R> L, const R* __restrict__ u,
                                                             const R* __restrict__ tau, R* __restrict__ out,
                                                             R scale) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+    constexpr int N2 = N * N, N3 = N2 * N, NT = op_threads<N>();
+    static_assert(NT >= N3 && NT >= 6 * N2, "node and face phases take one pass");
     __shared__ R su[3 * N3];          // u
     __shared__ R sG[9 * N3];          // reference derivatives; later the volume fluxes F, then D^T F
     __shared__ R sFT[6 * 3 * N2];     // per face node: interior traction, then -w J^Sigma (n Y S)*
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     if (tid >= 64) {
         const int t = tid - 64;
         const R wq = L.w[min(t, N - 1)];
-        stage_to_lds<3 * N3, line_threads<N>() - 64>(su, ue, t);
+        stage_to_lds<3 * N3, NT - 64>(su, ue, t);
         sw[min(t, N - 1)] = wq;
         swi[min(t, N - 1)] = R(1) / wq;
     } else {
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     }
     const R c11 = sown[0], c12 = sown[1], c44 = sown[2];
     // 1. line lanes: reference derivatives of u
-    ref_derivatives<N>(L, su, sG, tid);
+    ref_derivatives<N, R, NT>(L, su, sG, tid);
     __syncthreads();
     // 2. node lanes: unlifted gradient and stress; interior traction on each face slot.
     // Only this lane reads its node's derivatives, so S is parked in those slots.
@@ -267,9 +269,10 @@ __global__ __launch_bounds__(line_threads<N>(), (apply_waves<N, R>())) void k_ap
     __syncthreads();
     // 5. weak divergence sum_m D_m^T F^m, one lane per line: F^m_c along a line is
     // read by that line's lane only, so each lane overwrites its line in place
-    if (tid < 9 * N2) {
+#pragma unroll
+    for (int t = tid; t < 9 * N2; t += NT) {
         int d, c, base, stride;
-        line_of<N>(tid, d, c, base, stride);
+        line_of<N>(t, d, c, base, stride);
         R* line = sG + (d * 3 + c) * N3 + base;
         R v[N];
 #pragma unroll
@@ -306,7 +309,7 @@ template <typename R>
 hipError_t launch_traction(const LevelView<R>& L, const R* u, R* tau, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, R>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -315,7 +318,7 @@ template <typename R>
 hipError_t launch_apply(const LevelView<R>& L, const R* u, const R* tau, R* out, R scale, hipStream_t s) {
     return dispatch_n(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, R>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }
@@ -324,7 +327,7 @@ template <>
 hipError_t launch_traction<Dual>(const LevelView<Dual>& L, const Dual* u, Dual* tau, hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, Dual>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, Dual>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -334,7 +337,7 @@ hipError_t launch_apply<Dual>(const LevelView<Dual>& L, const Dual* u, const Dua
                               hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, Dual>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }
@@ -343,7 +346,7 @@ template <>
 hipError_t launch_traction<DD>(const LevelView<DD>& L, const DD* u, DD* tau, hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_traction<NN, DD>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau);
+        hipLaunchKernelGGL((k_traction<NN, DD>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau);
         return hipGetLastError();
     });
 }
@@ -352,7 +355,7 @@ template <>
 hipError_t launch_apply<DD>(const LevelView<DD>& L, const DD* u, const DD* tau, DD* out, DD scale, hipStream_t s) {
     return dispatch_dual(L.N, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
-        hipLaunchKernelGGL((k_apply<NN, DD>), dim3(L.E), dim3(line_threads<NN>()), 0, s, L, u, tau, out, scale);
+        hipLaunchKernelGGL((k_apply<NN, DD>), dim3(L.E), dim3(op_threads<NN>()), 0, s, L, u, tau, out, scale);
         return hipGetLastError();
     });
 }
