@@ -31,10 +31,25 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+# Host code built with AddressSanitizer and UndefinedBehaviorSanitizer (device
+# code unchanged): for checking the host-side calls (mesh, geometry, hierarchy
+# and smoother planning) on the CPU.  Load the result with the ASan runtime
+# preloaded.
+SANITIZE_FLAGS = [
+    "-O1", "-g",
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(HERE, "..", "include"), *srcs, "-o", tmp]
+    target = out or LIB
+    tmp = target + ".tmp"
+    flags = [f for f in HIPCC_FLAGS if not (sanitize and f == "-O3")] + (SANITIZE_FLAGS if sanitize else [])
+    cmd = [hipcc(), *flags, "-I", os.path.join(HERE, "..", "include"), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,8 +58,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed")
     if verbose and r.stderr:
         sys.stderr.write(r.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -31,7 +31,7 @@ __all__ = ["NoiseObjective", "TargetObjective", "DesignResult", "optimize", "fix
 
 
 class NoiseObjective:
-    """S_x of eq. fdt with one loss angle per layer: linear in U, so
+    """S_x of eqs. thermalnoise and wdiss with one loss angle per layer: linear in U, so
     dS_x/dU_k is S_x of the k-th unit vector."""
 
     def __init__(self, phi: Sequence[float], T: float, f: float):
