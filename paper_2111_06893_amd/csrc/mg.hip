@@ -428,20 +428,27 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
     const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
     const R* Ac = A + (size_t)c * n * n;
     const R* Bc = in + (size_t)c * n * ncol;
-    // the next K chunk is fetched into registers while the current one is multiplied
+    // the next K chunk is fetched into registers while the current one is
+    // multiplied: every load reads a clamped (valid) index, and the values
+    // outside the matrices are zeroed only when stored to LDS, after the
+    // products, so that no select waits on a load in flight (zeroing at the
+    // load made the kernel 1.8x slower; per-load branches cost 8 %)
     R ra[LA], rb[LB];
+    bool va[LA], vb[LB];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
             const int kg = k0 + q / kGM, rg = row0 + q % kGM;
-            ra[t] = (kg < n && rg < n) ? Ac[(size_t)kg * n + rg] : R(0);
+            ra[t] = Ac[(size_t)min(kg, n - 1) * n + min(rg, n - 1)];
+            va[t] = kg < n && rg < n;
         }
 #pragma unroll
         for (int t = 0; t < LB; ++t) {
             const int q = tid + 256 * t;
             const int kg = k0 + q / kGN, cg = col0 + q % kGN;
-            rb[t] = (kg < n && cg < ncol) ? Bc[(size_t)kg * ncol + cg] : R(0);
+            rb[t] = Bc[(size_t)min(kg, n - 1) * ncol + min(cg, ncol - 1)];
+            vb[t] = kg < n && cg < ncol;
         }
     };
     typename Acc::type acc[2][2];
@@ -474,26 +481,34 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
             const int q = tid + 256 * t;
-            As[q / kGM][q % kGM] = ra[t];
+            As[q / kGM][q % kGM] = va[t] ? ra[t] : R(0);
         }
 #pragma unroll
         for (int t = 0; t < LB; ++t) {
             const int q = tid + 256 * t;
-            Bs[q / kGN][q % kGN] = rb[t];
+            Bs[q / kGN][q % kGN] = vb[t] ? rb[t] : R(0);
         }
         __syncthreads();
         if (k0 + kGK < n) fetch(k0 + kGK);
+        // fragments of the next K step read from LDS while this step's products run
+        R af[2][2], bf[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[0][a] = As[lane / 16][wr + 16 * a + lane % 16];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[0][b] = Bs[lane / 16][wc + 16 * b + lane % 16];
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
-            R af[2], bf[2];
+            const int cur = (ks / 4) & 1, nx = cur ^ 1;
+            if (ks + 4 < kGK) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[ks + lane / 16][wr + 16 * a + lane % 16];
+                for (int a = 0; a < 2; ++a) af[nx][a] = As[ks + 4 + lane / 16][wr + 16 * a + lane % 16];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + lane / 16][wc + 16 * b + lane % 16];
+                for (int b = 0; b < 2; ++b) bf[nx][b] = Bs[ks + 4 + lane / 16][wc + 16 * b + lane % 16];
+            }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = Acc::step(af[a], bf[b], acc[a][b]);
+                for (int b = 0; b < 2; ++b) acc[a][b] = Acc::step(af[cur][a], bf[cur][b], acc[a][b]);
         }
         __syncthreads();
     }
