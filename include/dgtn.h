@@ -52,7 +52,7 @@ typedef enum {
     DGTN_ENAN = -6      /* NaN/Inf met in the solver                       */
 } dgtn_status;
 
-enum { DGTN_DOMAIN_CYLINDER = 0, DGTN_DOMAIN_BOX = 1 };
+enum { DGTN_DOMAIN_CYLINDER = 0, DGTN_DOMAIN_BOX = 1, DGTN_DOMAIN_COLUMNS = 2 };
 enum { DGTN_MAT_ISO = 0, DGTN_MAT_CUBIC = 1 };
 /* Boundary conditions (Sec. 2.2.4, eqs. bc, BCfixed, BCfree). */
 enum { DGTN_BC_DIRICHLET = 1, DGTN_BC_PRESSURE = 2, DGTN_BC_FREE = 3 };
@@ -79,10 +79,19 @@ typedef struct {
 /* Problem description (Sec. 2.1 and 2.2.1).  Cylinder: radius R, five blocks
  * (centre square of half-width R/(2 sqrt 2) and four wedges blending its edges
  * into the arc), each split 2^refine x 2^refine.  Box:
- * [-Lx/2, Lx/2] x [-Ly/2, Ly/2] with nx x ny columns.  In z the layers are
- * stacked from the loaded face z = 0 downward.  Load: Gaussian pressure of
- * eq. laserbeam with total force F0, width r0, centred at (xc, yc), on faces
- * tagged DGTN_BC_PRESSURE.  penalty is C of eq. penalty (100 in the paper). */
+ * [-Lx/2, Lx/2] x [-Ly/2, Ly/2] with nx x ny columns.  Columns: an explicit
+ * 2D mesh of n_columns quadrilateral columns, each given by its isoparametric
+ * map of degree map_order (1..8): columns_xy[c][d][j][i] (d = 0 x, 1 y; i
+ * along xi fastest, j along eta) is the map at the LGL points (x_i, x_j) of
+ * degree map_order, with det > 0 (counter-clockwise); the library takes the
+ * map at its own nodes by Lagrange interpolation, matches neighbouring
+ * columns by their edge nodes (conforming edges only) and tags the unmatched
+ * edges as the side boundary; refine must be 0 (the multigrid then coarsens in
+ * degree and across layers only).  columns_xy is copied by dgtn_create.  In z
+ * the layers are stacked from the loaded face z = 0 downward.  Load: Gaussian
+ * pressure of eq. laserbeam with total force F0, width r0, centred at (xc, yc),
+ * on faces tagged DGTN_BC_PRESSURE.  penalty is C of eq. penalty (100 in the
+ * paper). */
 typedef struct {
     int domain;
     double R;
@@ -97,6 +106,9 @@ typedef struct {
     double F0, r0, xc, yc;
     int bc_top, bc_bottom, bc_side;
     double penalty;
+    int n_columns;            /* DGTN_DOMAIN_COLUMNS only                      */
+    int map_order;
+    const double* columns_xy; /* [n_columns][2][map_order + 1][map_order + 1]  */
 } dgtn_problem;
 
 typedef struct {

@@ -98,6 +98,29 @@ def columns(spec):
                     y = -0.5 * Ly + (t + 0.5 * (eta + 1.0)) * (Ly / ny)
                     return x, y
                 cols.append(fmap)
+    elif spec["domain"] == "columns":
+        # explicit 2D mesh: each column's map given at the LGL points of degree q,
+        # taken anywhere by Lagrange interpolation through those points
+        q = int(spec["columns"]["order"])
+        xs, _ = lgl.nodes_weights(q + 1)
+        maps = np.asarray(spec["columns"]["xy"], dtype=np.float64).reshape(-1, 2, q + 1, q + 1)
+
+        def basis(t):
+            t = np.asarray(t, dtype=np.float64)
+            out = np.ones(t.shape + (q + 1,))
+            for k in range(q + 1):
+                for m in range(q + 1):
+                    if m != k:
+                        out[..., k] *= (t - xs[m]) / (xs[k] - xs[m])
+            return out
+
+        for c in range(maps.shape[0]):
+            def fmap(xi, eta, m=maps[c]):
+                Li, Lj = basis(xi), basis(eta)
+                x = np.einsum("...i,...j,ji->...", Li, Lj, m[0])
+                y = np.einsum("...i,...j,ji->...", Li, Lj, m[1])
+                return x, y
+            cols.append(fmap)
     else:
         raise ValueError(spec["domain"])
     return cols

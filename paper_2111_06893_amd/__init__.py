@@ -36,14 +36,23 @@ def problem_struct(spec):
         lays[i] = _lib.Layer(l["thickness"], l["n_elem"], l["ratio"], l["material"])
     ld = spec["load"]
     bc = spec["bc"]
-    box = spec["domain"] == "box"
+    domain = {"cylinder": 0, "box": 1, "columns": 2}[spec["domain"]]
+    cxy, n_columns, order = None, 0, 0
+    if domain == 2:
+        order = int(spec["columns"]["order"])
+        cxy = np.ascontiguousarray(spec["columns"]["xy"], dtype=np.float64)
+        if cxy.ndim != 4 or cxy.shape[1:] != (2, order + 1, order + 1):
+            raise ValueError("columns xy must be [n_columns, 2, order + 1, order + 1]")
+        n_columns = cxy.shape[0]
     p = _lib.ProblemC(
-        domain=1 if box else 0, R=spec.get("R", 1.0), refine=0 if box else spec["refine"],
+        domain=domain, R=spec.get("R", 1.0), refine=spec["refine"] if domain == 0 else 0,
         Lx=spec.get("Lx", 1.0), Ly=spec.get("Ly", 1.0), nx=spec.get("nx", 1), ny=spec.get("ny", 1),
         p=spec["p"], n_layers=len(lays), layers=lays, n_materials=len(mats), materials=mats,
         F0=ld["F0"], r0=ld["r0"], xc=ld["xc"], yc=ld["yc"],
-        bc_top=bc["top"], bc_bottom=bc["bottom"], bc_side=bc["side"], penalty=spec["penalty"])
-    return p, (mats, lays)
+        bc_top=bc["top"], bc_bottom=bc["bottom"], bc_side=bc["side"], penalty=spec["penalty"],
+        n_columns=n_columns, map_order=order,
+        columns_xy=cxy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if cxy is not None else None)
+    return p, (mats, lays, cxy)
 
 
 def _material_struct(m):

@@ -27,7 +27,8 @@ class ProblemC(ctypes.Structure):
                 ("layers", ctypes.POINTER(Layer)), ("n_materials", c_int),
                 ("materials", ctypes.POINTER(Material)), ("F0", c_double), ("r0", c_double),
                 ("xc", c_double), ("yc", c_double), ("bc_top", c_int), ("bc_bottom", c_int),
-                ("bc_side", c_int), ("penalty", c_double)]
+                ("bc_side", c_int), ("penalty", c_double), ("n_columns", c_int), ("map_order", c_int),
+                ("columns_xy", ctypes.POINTER(c_double))]
 
 
 class Info(ctypes.Structure):

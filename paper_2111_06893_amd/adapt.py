@@ -79,6 +79,8 @@ def refine_disk(spec: dict) -> dict:
     """A copy of spec refined once across the disk, everywhere: the cylinder's
     disk mesh one level finer (four times the columns), the box's columns halved
     in both directions.  Conforming, like refinement in z."""
+    if spec["domain"] == "columns":
+        raise ValueError("an explicit 2D mesh is not refined across the disk here")
     s = copy.deepcopy(spec)
     if s["domain"] == "cylinder":
         s["refine"] += 1
@@ -156,5 +158,10 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
 
 def _n_dof(spec: dict) -> int:
     """Unknowns of a mesh description: 3 (p + 1)^3 per element."""
-    cols = 5 * 4 ** spec["refine"] if spec["domain"] == "cylinder" else spec["nx"] * spec["ny"]
+    if spec["domain"] == "cylinder":
+        cols = 5 * 4 ** spec["refine"]
+    elif spec["domain"] == "columns":
+        cols = len(spec["columns"]["xy"])
+    else:
+        cols = spec["nx"] * spec["ny"]
     return 3 * cols * sum(l["n_elem"] for l in spec["layers"]) * (spec["p"] + 1) ** 3

@@ -168,8 +168,18 @@ static bool material_ok(const dgtn_material& m) {
 static dgtn_status validate(const dgtn_problem* p) {
     if (!p) { set_error("null problem"); return DGTN_EINVAL; }
     if (p->p < 1 || p->p > 7) { set_error("p must be in 1..7"); return DGTN_EINVAL; }
-    if (p->domain != DGTN_DOMAIN_CYLINDER && p->domain != DGTN_DOMAIN_BOX) {
+    if (p->domain != DGTN_DOMAIN_CYLINDER && p->domain != DGTN_DOMAIN_BOX && p->domain != DGTN_DOMAIN_COLUMNS) {
         set_error("unknown domain"); return DGTN_EINVAL;
+    }
+    if (p->domain == DGTN_DOMAIN_COLUMNS) {
+        if (p->n_columns < 1 || p->map_order < 1 || p->map_order > 8 || !p->columns_xy) {
+            set_error("columns domain: need n_columns >= 1, map_order in 1..8 and the column maps");
+            return DGTN_EINVAL;
+        }
+        if (p->refine != 0) { set_error("columns domain: refine must be 0"); return DGTN_EINVAL; }
+        const size_t n = (size_t)p->n_columns * 2 * (p->map_order + 1) * (p->map_order + 1);
+        for (size_t q = 0; q < n; ++q)
+            if (!std::isfinite(p->columns_xy[q])) { set_error("columns domain: non-finite node"); return DGTN_EINVAL; }
     }
     if (p->domain == DGTN_DOMAIN_CYLINDER && !(p->R > 0)) { set_error("R must be > 0"); return DGTN_EINVAL; }
     if (p->domain == DGTN_DOMAIN_BOX && (!(p->Lx > 0) || !(p->Ly > 0) || p->nx < 1 || p->ny < 1)) {
@@ -256,6 +266,12 @@ dgtn_status dgtn_create(const dgtn_problem* p, dgtn_ctx** out) {
         P.bc_bottom = p->bc_bottom;
         P.bc_side = p->bc_side;
         P.penalty = p->penalty;
+        if (P.domain == DGTN_DOMAIN_COLUMNS) {
+            P.n_cols_user = p->n_columns;
+            P.map_order = p->map_order;
+            const size_t n = (size_t)p->n_columns * 2 * (p->map_order + 1) * (p->map_order + 1);
+            P.col_xy.assign(p->columns_xy, p->columns_xy + n);
+        }
         c->matc = material_constants(P);
         c->y_ref = 0;
         for (size_t m = 0; m < c->matc.size(); m += 3) c->y_ref = std::max(c->y_ref, c->matc[m]);

@@ -117,6 +117,21 @@ void column_point(const Problem& P, int refine, int col, double xi, double eta,
         const double XB = -1.0 + (s + 0.5 * (xi + 1.0)) * (2.0 / m);
         const double EB = -1.0 + (t + 0.5 * (eta + 1.0)) * (2.0 / m);
         cylinder_block(block, P.R, XB, EB, x, y);
+    } else if (P.domain == DGTN_DOMAIN_COLUMNS) {
+        // the given map of degree q at (xi, eta) by Lagrange interpolation over its LGL points
+        const int q1 = P.map_order + 1;
+        static thread_local Lgl map;
+        if (map.N != q1) map = make_lgl(q1);
+        const auto lx = lagrange_matrix(map, {xi});
+        const auto ly = lagrange_matrix(map, {eta});
+        const double* m = &P.col_xy[(size_t)col * 2 * q1 * q1];
+        x = y = 0.0;
+        for (int b = 0; b < q1; ++b)
+            for (int a = 0; a < q1; ++a) {
+                const double wgt = ly[b] * lx[a];
+                x += wgt * m[b * q1 + a];
+                y += wgt * m[q1 * q1 + b * q1 + a];
+            }
     } else {
         // refine multiplies the box resolution by 2^refine in each direction
         const int nx = P.nx << refine, ny = P.ny << refine;
@@ -128,6 +143,7 @@ void column_point(const Problem& P, int refine, int col, double xi, double eta,
 
 int columns_of(const Problem& P, int refine) {
     if (P.domain == DGTN_DOMAIN_CYLINDER) return 5 * (1 << (2 * refine));
+    if (P.domain == DGTN_DOMAIN_COLUMNS) return P.n_cols_user;
     return (P.nx << refine) * (P.ny << refine);
 }
 
@@ -284,6 +300,48 @@ Level build_level(const Problem& P, int p, int refine, int p0, int r0) {
             L.cnf[A.c * 4 + A.f] = B.f | (flip << 2);
             L.cnbr[B.c * 4 + B.f] = A.c;
             L.cnf[B.c * 4 + B.f] = A.f | (flip << 2);
+        }
+    }
+    // An unmatched edge is a boundary edge.  Two unmatched edges with the same two
+    // end points (a shared edge whose nodes differ), or an unmatched edge whose
+    // end point lies inside another (a hanging node), would be a crack between
+    // columns: reject those meshes instead of treating them as free boundaries.
+    {
+        std::vector<int> open;
+        for (int k = 0; k < L.n_cols * 4; ++k)
+            if (L.cnbr[k] < 0) open.push_back(k);
+        auto end_pts = [&](int k, double p[2][2]) {
+            edge_pt(k / 4, k % 4, 0, p[0][0], p[0][1]);
+            edge_pt(k / 4, k % 4, N - 1, p[1][0], p[1][1]);
+        };
+        auto near = [&](const double* a, const double* b) { return std::hypot(a[0] - b[0], a[1] - b[1]) <= tol; };
+        for (size_t a = 0; a < open.size(); ++a) {
+            double pa[2][2];
+            end_pts(open[a], pa);
+            for (size_t b = 0; b < open.size(); ++b) {
+                if (a == b) continue;
+                double pb[2][2];
+                end_pts(open[b], pb);
+                if ((near(pa[0], pb[0]) && near(pa[1], pb[1])) || (near(pa[0], pb[1]) && near(pa[1], pb[0])))
+                    throw std::runtime_error("non-conforming side faces (a shared edge whose nodes differ)");
+                // end points of a strictly inside the polyline of b's edge nodes
+                for (int s = 0; s < 2; ++s) {
+                    if (near(pa[s], pb[0]) || near(pa[s], pb[1])) continue;
+                    for (int t = 0; t + 1 < N; ++t) {
+                        double x0, y0, x1, y1;
+                        edge_pt(open[b] / 4, open[b] % 4, t, x0, y0);
+                        edge_pt(open[b] / 4, open[b] % 4, t + 1, x1, y1);
+                        const double dx = x1 - x0, dy = y1 - y0, l2 = dx * dx + dy * dy;
+                        if (!(l2 > 0)) continue;
+                        const double u = ((pa[s][0] - x0) * dx + (pa[s][1] - y0) * dy) / l2;
+                        if (u < 0 || u > 1) continue;
+                        // the polyline is a chord of a curved edge: allow its sagitta
+                        const double d = std::hypot(x0 + u * dx - pa[s][0], y0 + u * dy - pa[s][1]);
+                        if (d <= tol + 0.05 * std::sqrt(l2))
+                            throw std::runtime_error("non-conforming side faces (a hanging node)");
+                    }
+                }
+            }
         }
     }
     for (int k = 0; k < L.n_cols * 4; ++k)

@@ -77,6 +77,10 @@ struct Problem {
     double F0 = 1, r0 = 0.1, xc = 0, yc = 0;
     int bc_top = DGTN_BC_PRESSURE, bc_bottom = DGTN_BC_DIRICHLET, bc_side = DGTN_BC_FREE;
     double penalty = 100;
+    // explicit 2D mesh (DGTN_DOMAIN_COLUMNS): column maps of degree map_order at
+    // the LGL points, [n_cols][2][(map_order + 1)^2]
+    int n_cols_user = 0, map_order = 0;
+    std::vector<double> col_xy;
 };
 
 // Builds the level of polynomial degree p with `refine` horizontal splits.

@@ -119,3 +119,84 @@ def test_device_calls_need_a_device():
     P = dgtn.Problem(W.config1())
     with pytest.raises(dgtn.DgtnError, match="no HIP device"):
         P.bind()
+
+
+def _annulus_columns(order, n_r=2, n_t=6, r_in=0.3, r_out=1.0):
+    """Curved columns of degree `order`: an annulus split into n_r x n_t sectors,
+    the map r(xi), theta(eta) sampled at the oracle's LGL points."""
+    from oracle import lgl
+    xs, _ = lgl.nodes_weights(order + 1)
+    out = np.zeros((n_r * n_t, 2, order + 1, order + 1))
+    for t in range(n_t):
+        for s in range(n_r):
+            for j in range(order + 1):
+                th = 2 * np.pi * (t + 0.5 * (xs[j] + 1)) / n_t
+                for i in range(order + 1):
+                    r = r_in + (r_out - r_in) * (s + 0.5 * (xs[i] + 1)) / n_r
+                    out[t * n_r + s, 0, j, i] = r * np.cos(th)
+                    out[t * n_r + s, 1, j, i] = r * np.sin(th)
+    return out
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.columns_mesh(W.quad_columns(3, 2, 1.2, 0.8, jitter=0.25, seed=3), p=4,
+                           layers=[{"thickness": 0.2, "n_elem": 2, "ratio": 1.5, "material": 0}]),
+    lambda: W.columns_mesh(_annulus_columns(3), order=3, p=5),
+    lambda: W.columns_mesh(_annulus_columns(6), order=6, p=2)])
+def test_explicit_mesh_matches_oracle(make):
+    # the library's and the oracle's meshes from the same column maps: both interpolate the
+    # given nodes at their own LGL points and match neighbours by coordinates
+    spec = make()
+    P = dgtn.Problem(spec)
+    assert P.shape == W.field_shape(spec)
+    xyz = P.node_coords()
+    ref = omesh.build(spec).xyz
+    assert np.abs(xyz - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_explicit_mesh_reproduces_the_box():
+    # undisplaced quad columns are the box description's own columns
+    box = W.box(nx=3, ny=2, Lx=1.2, Ly=0.8, p=3)
+    cols = W.columns_mesh(W.quad_columns(3, 2, 1.2, 0.8), p=3)
+    a, b = dgtn.Problem(box).node_coords(), dgtn.Problem(cols).node_coords()
+    assert np.abs(a - b).max() < 1e-15
+
+
+def _quad(x0, x1, y0, y1):
+    """Degree-1 map of the rectangle [x0, x1] x [y0, y1] (corners at xi, eta = -1, 1)."""
+    return np.array([[[x0, x1], [x0, x1]], [[y0, y0], [y1, y1]]])
+
+
+def test_explicit_mesh_is_validated():
+    import ctypes
+    from paper_2111_06893_amd._lib import check
+    xy = W.quad_columns(2, 2)
+    st, keep = dgtn.problem_struct(W.columns_mesh(xy))
+    st.refine = 1
+    with pytest.raises(dgtn.DgtnError, match="refine"):
+        check(dgtn.load().dgtn_create(ctypes.byref(st), ctypes.byref(ctypes.c_void_p())))
+    flipped = xy[:, :, :, ::-1].copy()          # clockwise columns: det J < 0
+    with pytest.raises(dgtn.DgtnError, match="EMESH"):
+        dgtn.Problem(W.columns_mesh(flipped))
+    bad = xy.copy()
+    bad[0, 0, 0, 0] = np.nan
+    with pytest.raises(dgtn.DgtnError, match="non-finite"):
+        dgtn.Problem(W.columns_mesh(bad))
+    # a hanging node: two columns on top of one (a T-junction) would be a crack
+    tee = np.stack([_quad(-0.5, 0.5, -0.5, 0.0), _quad(-0.5, 0.0, 0.0, 0.5), _quad(0.0, 0.5, 0.0, 0.5)])
+    with pytest.raises(dgtn.DgtnError, match="hanging node"):
+        dgtn.Problem(W.columns_mesh(tee))
+    # a shared edge that the two columns curve differently (degree-2 maps, same end points)
+    from oracle import lgl
+    xs, _ = lgl.nodes_weights(3)
+    two = np.zeros((2, 2, 3, 3))
+    for c, (x0, x1) in enumerate(((-0.5, 0.0), (0.0, 0.5))):
+        for j in range(3):
+            for i in range(3):
+                two[c, 0, j, i] = x0 + (x1 - x0) * 0.5 * (xs[i] + 1)
+                two[c, 1, j, i] = -0.5 + 0.5 * (xs[j] + 1)
+    two[0, 0, 1, 2] += 0.05                     # bulge the right edge of the first column only
+    with pytest.raises(dgtn.DgtnError, match="non-conforming"):
+        dgtn.Problem(W.columns_mesh(two, order=2))
+    two[1, 0, 1, 0] += 0.05                     # the same bulge on both sides: conforming
+    dgtn.Problem(W.columns_mesh(two, order=2))

@@ -128,6 +128,44 @@ def box(nx=2, ny=2, Lx=1.0, Ly=1.0, layers=None, materials=None, p=3, bc=None,
     return spec
 
 
+def quad_columns(nx, ny, Lx=1.0, Ly=1.0, jitter=0.0, seed=0):
+    """Column maps of degree 1 of an nx x ny quadrilateral mesh of the box
+    [-Lx/2, Lx/2] x [-Ly/2, Ly/2] whose interior vertices are displaced by up to
+    `jitter` times the cell size (uniform, seeded): array [nx * ny, 2, 2, 2],
+    entry [c, d, j, i] the coordinate d of the corner at xi = -1 + 2 i,
+    eta = -1 + 2 j of column c = t * nx + s (counter-clockwise)."""
+    hx, hy = Lx / nx, Ly / ny
+    VX, VY = np.meshgrid(-0.5 * Lx + hx * np.arange(nx + 1), -0.5 * Ly + hy * np.arange(ny + 1), indexing="xy")
+    g = np.random.default_rng(seed)
+    inner = np.zeros_like(VX, dtype=bool)
+    inner[1:-1, 1:-1] = True
+    VX = VX + np.where(inner, jitter * hx * g.uniform(-1.0, 1.0, VX.shape), 0.0)
+    VY = VY + np.where(inner, jitter * hy * g.uniform(-1.0, 1.0, VY.shape), 0.0)
+    out = np.zeros((nx * ny, 2, 2, 2))
+    for t in range(ny):
+        for s in range(nx):
+            for j in range(2):
+                for i in range(2):
+                    out[t * nx + s, 0, j, i] = VX[t + j, s + i]
+                    out[t * nx + s, 1, j, i] = VY[t + j, s + i]
+    return out
+
+
+def columns_mesh(xy, order=1, layers=None, materials=None, p=3, bc=None, load=None):
+    """Problem on an explicit 2D mesh: xy [n_columns, 2, order + 1, order + 1],
+    each column's map at the LGL points of degree `order` (see quad_columns),
+    extruded through the layers."""
+    spec = _base(domain="columns", refine=0, p=p)
+    spec["columns"] = {"order": int(order), "xy": np.asarray(xy, dtype=np.float64)}
+    spec["layers"] = layers or [{"thickness": 1.0, "n_elem": 1, "ratio": 1.0, "material": 0}]
+    spec["materials"] = materials or [dict(FUSED_SILICA)]
+    if bc is not None:
+        spec["bc"] = dict(bc)
+    if load is not None:
+        spec["load"] = dict(load)
+    return spec
+
+
 def with_overrides(spec, **kw):
     out = copy.deepcopy(spec)
     out.update(kw)
@@ -141,6 +179,8 @@ CONFIGS = {"config1": config1, "config2": config2, "config3": config3,
 def n_columns(spec):
     if spec["domain"] == "cylinder":
         return 5 * 4 ** spec["refine"]
+    if spec["domain"] == "columns":
+        return len(spec["columns"]["xy"])
     return spec["nx"] * spec["ny"]
 
 
