@@ -142,7 +142,7 @@ typedef struct {
     int krylov;               /* DGTN_KRYLOV_FGMRES or DGTN_KRYLOV_FCG          */
     int overlap;              /* column-subdomain overlap in node lines (0..3)  */
     int residual_precision;   /* true residual b - A u: 64 (or 0) FP64, 128
-                                 double-double (dgtn_residual; p <= 6)          */
+                                 double-double (dgtn_residual)                  */
 } dgtn_solve_opts;
 
 /* Additive-Schwarz subdomains: one element, or one whole z-column of elements
@@ -223,7 +223,7 @@ dgtn_status dgtn_solve(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double*
  * of a double u (eps |A| |u|, large on thin layers through the interior-penalty
  * terms of eq. penalty).  dgtn_solve uses it for its true residual when
  * opts->residual_precision is 128.  b, u, r: device double, n_dof values; r
- * must not alias u.  Available for p <= 6 (DGTN_EINVAL otherwise). */
+ * must not alias u. */
 dgtn_status dgtn_residual(dgtn_ctx* ctx, const double* b, const double* u, double* r, hipStream_t stream);
 
 /* z = M^{-1} v: one application of the solver's preconditioner (the V-cycle
@@ -309,8 +309,8 @@ dgtn_status dgtn_energy_grad(dgtn_ctx* ctx, const double* u, const double* w_lay
  * parameters leave A and K unchanged.  A_theta u and K_w,theta are evaluated
  * exactly by the operator and energy kernels on dual numbers, b_theta by the
  * load kernel with the derivative of the pressure profile.  u, lam: device
- * double; dJ: host, n_params values.  Available for p <= 6 (DGTN_EINVAL
- * otherwise, and for an unknown kind or index).  Synchronises the stream. */
+ * double; dJ: host, n_params values.  DGTN_EINVAL for an unknown kind or
+ * index.  Synchronises the stream. */
 dgtn_status dgtn_grad(dgtn_ctx* ctx, const double* u, const double* lam, const double* w_layers,
                       int n_params, const dgtn_param* params, double* dJ, hipStream_t stream);
 

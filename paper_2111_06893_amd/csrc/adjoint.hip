@@ -127,7 +127,7 @@ void plan_adjoint(dgtn_ctx* c, Layout& lay) {
     AdjointLayout& A = c->adj;
     const size_t N = L.N, N2 = N * N, n = ndof(L), ds = sizeof(Dual);
     A.wz = lay.take(8 * (size_t)L.n_z);
-    A.ok = L.N <= 7;
+    A.ok = L.N <= 8;
     if (!A.ok) return;
     A.u = lay.take(ds * n);
     A.Au = lay.take(ds * n);
@@ -204,7 +204,7 @@ extern "C" dgtn_status dgtn_grad(dgtn_ctx* c, const double* u, const double* lam
     }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     const AdjointLayout& A = c->adj;
-    if (!A.ok) { set_error("parameter derivatives are available for p <= 6"); return DGTN_EINVAL; }
+    if (!A.ok) { set_error("parameter derivatives are available for p <= 7"); return DGTN_EINVAL; }
     const Level& L = c->levels[0];
     const int nmat = (int)c->prob.materials.size(), nlay = (int)c->prob.layers.size();
     for (int i = 0; i < n_params; ++i) {

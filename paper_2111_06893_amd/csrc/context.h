@@ -13,7 +13,7 @@ namespace dgtn {
 
 // Workspace offsets of the adjoint's dual-number copies of the finest level.
 struct AdjointLayout {
-    bool ok = false;  // allocated (the dual kernels cover N <= 7)
+    bool ok = false;  // allocated (the dual kernels cover N <= 8)
     size_t wz = 0, u = 0, Au = 0, tau = 0, geo2 = 0, sig = 0, fnrm = 0, hz = 0, mat = 0, D = 0, w = 0, Ue = 0;
     size_t partial = 0, dots = 0;
     int nblk = 0;
@@ -22,7 +22,7 @@ struct AdjointLayout {
 // Workspace offsets of the double-double copies of the finest level's
 // coefficient tables (the extended-precision residual).
 struct ResidualLayout {
-    bool ok = false;  // available (the 16-byte kernels cover N <= 7)
+    bool ok = false;  // available (the 16-byte kernels cover N <= 8)
     size_t geo2 = 0, sig = 0, fnrm = 0, hz = 0, mat = 0, D = 0, w = 0;
 };
 

@@ -368,8 +368,9 @@ hipError_t dispatch_n(int N, F&& f) {
     }
 }
 
-// The dual-number kernels serve the parameter derivatives up to p = 6 (their
-// LDS footprint doubles); larger N return hipErrorInvalidValue.
+// The 16-byte kernels (dual numbers of the parameter derivatives, double-double
+// numbers of the extended-precision residual) for every degree p = 1..7: their
+// LDS footprint doubles, 135 KB at N = 8, within gfx950's 160 KB.
 template <typename F>
 hipError_t dispatch_dual(int N, F&& f) {
     switch (N) {
@@ -379,6 +380,7 @@ hipError_t dispatch_dual(int N, F&& f) {
         case 5: return f(std::integral_constant<int, 5>{});
         case 6: return f(std::integral_constant<int, 6>{});
         case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
         default: return hipErrorInvalidValue;
     }
 }

@@ -1360,7 +1360,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         set_error("residual_precision must be 64 or 128"); return DGTN_EINVAL;
     }
     if (opts->residual_precision == 128 && !c->res.ok) {
-        set_error("the double-double residual covers p <= 6"); return DGTN_EINVAL;
+        set_error("the double-double residual covers p <= 7"); return DGTN_EINVAL;
     }
     const auto t0 = std::chrono::steady_clock::now();
     const bool verbose = std::getenv("DGTN_VERBOSE") != nullptr;

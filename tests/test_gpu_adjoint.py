@@ -270,3 +270,28 @@ def test_coated_cylinder_gradient_central_differences():
         fd = (f[1] - f[0]) / (2 * h)
         print(f"  {kind}[{index}] adjoint {a:.10e} central {fd:.10e} rel {a / fd - 1:+.2e}", flush=True)
         assert abs(a / fd - 1) < 1e-6, (kind, index, a, fd)
+
+
+def test_gradient_at_the_highest_degree_matches_oracle():
+    # p = 7 (N = 8): the dual-number kernels at their largest size (136 KB of LDS) against the
+    # oracle's gradient on a three-element box with a cubic coating (dense refined solves)
+    g = _golden_gradients()["box_p7"]
+    spec, params, w = g["spec"], [tuple(p) for p in g["params"]], np.array(g["w_layers"])
+    print("[adjoint] box p=7 against the oracle", flush=True)
+    P = dgtn.Problem(spec)
+    o = dgtn.default_opts(64, rtol=1e-14, max_iter=20000)
+    u, st = P.solve(opts=o, raise_on_noconv=False)
+    assert st.rel_res < 1e-9
+    J = float(np.dot(w, P.energy(u)))
+    lam, st2 = P.solve(b=P.energy_grad(u, w), opts=o, raise_on_noconv=False)
+    assert st2.rel_res < 1e-9
+    dJ = P.grad(u, lam, params, w)
+    assert abs(J / g["J"] - 1) < 1e-11, (J, g["J"])
+    for (kind, index), a, b in zip(params, dJ, g["dJ"]):
+        print(f"  {kind}[{index}] {a:.12e} oracle {b:.12e} rel {a / b - 1:+.2e}", flush=True)
+        assert abs(a / b - 1) < (1e-10 if kind in ("c11", "c12", "c44", "youngs") else 1e-9), (kind, index, a, b)
+    # and the double-double residual at this degree agrees with FP64 to its rounding
+    b = P.rhs()
+    r = P.residual(u, b)
+    r64 = b - P.apply(u)
+    assert float(torch.linalg.norm(r - r64)) < 1e-2 * float(torch.linalg.norm(r64))
