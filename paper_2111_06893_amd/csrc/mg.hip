@@ -413,8 +413,15 @@ template <> struct MfmaAcc<float> {
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
 // W: patch width (the eigenvalue division splits the column index by W and W^2,
 // compile-time constants here); div = 0 takes W = 0.
+// waves per SIMD asked of the compiler: five in FP32 (96 registers; four would
+// leave 2400 workgroups of the forty-layer level in three rounds of 1024), three in FP64
+template <typename R>
+constexpr int gemm_waves() {
+    return sizeof(R) == 4 ? 5 : 3;
+}
+
 template <typename R, int W, int div>
-__global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ A,
+__global__ __launch_bounds__(256, gemm_waves<R>()) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ A,
                                                        const R* __restrict__ in, R* __restrict__ out,
                                                        const R* __restrict__ lz, const R* __restrict__ lam,
                                                        const R* __restrict__ rat) {
@@ -457,24 +464,19 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
     fetch(0);
-    // denominators of this lane's outputs (indices clamped: outputs past n or
-    // ncol are computed but not stored)
-    R den[2][2][4];
+    // in-plane part of the denominators of this lane's outputs, whose table reads
+    // depend on one another, fetched before the K loop (indices clamped: outputs
+    // past n or ncol are computed but not stored); the z-eigenvalues, single
+    // loads, are read after it, which keeps the registers at five waves per SIMD
+    R lxy[2];
     if constexpr (div) {
         constexpr int W2 = W * W;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int cg = min(col0 + wc + 16 * b + lane % 16, ncol - 1);
             const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
-            const R lxy = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
-                          rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int rg = min(row0 + wr + 16 * a + Acc::row(lane, q), n - 1);
-                    den[a][b][q] = lz[(size_t)c * n + rg] + lxy;
-                }
+            lxy[b] = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
+                     rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
         }
     }
     for (int k0 = 0; k0 < n; k0 += kGK) {
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(256) void k_col_gemm_mfma(int n, int ncol, const R*
                 const int rg = row0 + wr + 16 * a + Acc::row(lane, q);
                 if (rg >= n) continue;
                 R v = acc[a][b][q];
-                if constexpr (div) v /= den[a][b][q];
+                if constexpr (div) v /= lz[(size_t)c * n + rg] + lxy[b];
                 Oc[(size_t)rg * ncol + cg] = v;
             }
         }
