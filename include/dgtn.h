@@ -334,12 +334,16 @@ dgtn_status dgtn_energy_parts(dgtn_ctx* ctx, const double* u, double* parts, hip
  * over all faces.  faces selects the face families summed: DGTN_FACES_SIDE (the
  * four faces across the disk, logical xi and eta), DGTN_FACES_Z (the two faces
  * across the layers, logical zeta: the jumps that refinement in z reduces) or
- * DGTN_FACES_ALL; other values give DGTN_EINVAL.  u: device double, n_dof.
+ * DGTN_FACES_ALL, optionally or-ed with DGTN_FACES_PENALTY, which weights each
+ * face node's term by the penalty of eq. penalty at that node,
+ * sigma = C (p + 1)^2 / min(h_int, h_ext) (own h on Dirichlet faces): the jump
+ * part of the DG energy norm, in which a thin layer's jumps count in proportion
+ * to the penalty that acts on them.  Other values give DGTN_EINVAL.  u: device double, n_dof.
  * eta_elem: host, n_elem, element
  * order of u (may be null); eta_layers: host, n_layers, the per-layer sums in
  * fixed order (may be null; not both).  Lengths in the problem's units.
  * Synchronises the stream; DGTN_ENAN if a value is not finite. */
-enum { DGTN_FACES_SIDE = 1, DGTN_FACES_Z = 2, DGTN_FACES_ALL = 3 };
+enum { DGTN_FACES_SIDE = 1, DGTN_FACES_Z = 2, DGTN_FACES_ALL = 3, DGTN_FACES_PENALTY = 4 };
 dgtn_status dgtn_jump_indicator(dgtn_ctx* ctx, const double* u, int faces, double* eta_elem, double* eta_layers,
                                 hipStream_t stream);
 

@@ -286,17 +286,18 @@ class Problem:
                                    ctypes.byref(comp) if compliance else None, self._stream()))
         return (out, comp.value) if compliance else out
 
-    def jump_indicator(self, u, faces="all"):
+    def jump_indicator(self, u, faces="all", weight="jump"):
         """Face-jump indicator of adaptive refinement: (eta_e^2 per element in the
         element order of u, their per-layer sums), numpy, over the face family
-        `faces`: "side", "z" or "all"."""
+        `faces`: "side", "z" or "all"; weight "jump" (plain squared jumps) or
+        "penalty" (each term times the penalty sigma at its node)."""
         import torch
         self._ensure()
         self._check_field(u, torch.float64)
         eta = np.zeros(self.info.n_elem)
         lay = np.zeros(self.n_layers)
         dp = ctypes.POINTER(ctypes.c_double)
-        which = {"side": 1, "z": 2, "all": 3}[faces]
+        which = {"side": 1, "z": 2, "all": 3}[faces] | {"jump": 0, "penalty": 4}[weight]
         check(self.lib.dgtn_jump_indicator(self.ctx, ctypes.c_void_p(u.data_ptr()), which, eta.ctypes.data_as(dp),
                                            lay.ctypes.data_as(dp), self._stream()))
         return eta, lay

@@ -12,7 +12,10 @@ One step:
   2. eta_e^2, the face-jump indicator of dgtn_jump_indicator over the z-faces
      (the jumps between z-elements and on the fixed face: the side-face jumps
      measure the resolution across the disk, which refinement in z leaves as it
-     is), summed per layer;
+     is), each face's squared jump weighted by the penalty sigma = C N^2 / h
+     that acts on it (the jump term of the DG energy norm, so that a thin
+     layer's jumps count as much as the operator makes them cost), summed per
+     layer;
   3. mark the fewest layers whose indicators hold a fraction theta of the total
      (bulk marking, largest first);
   4. multiply their element counts across the thickness by `factor`, splitting
@@ -105,7 +108,7 @@ class AdaptStep:
 
 def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=None, tol: Optional[float] = None,
           max_elem: Optional[int] = 64, disk: bool = False, max_dof: Optional[int] = 50_000_000,
-          max_rel_res: float = 1e-8) -> List[AdaptStep]:
+          max_rel_res: float = 1e-8, weight: str = "penalty") -> List[AdaptStep]:
     """Solve-estimate-mark-refine for `steps` meshes (fewer if the total
     z-face indicator drops to tol, no layer can be refined further, or the
     next mesh would exceed max_dof unknowns).  With disk=True a step whose
@@ -114,7 +117,9 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
     under-resolved.  A solve that stops above rtol (at the FP64 residual floor
     of a finer mesh) is accepted up to the relative residual max_rel_res, which
     each step records: the layer energies are not stationary in u, so their
-    error is of first order in the residual."""
+    error is of first order in the residual.  weight "penalty" (default) weights
+    every face's squared jump by the penalty sigma at its nodes (the jump term of
+    the DG energy norm), "jump" leaves it plain."""
     o = opts if opts is not None else default_opts(32, rtol=1e-10)
     s = copy.deepcopy(spec)
     out: List[AdaptStep] = []
@@ -129,8 +134,8 @@ def adapt(spec: dict, steps: int = 4, theta: float = 0.5, factor: int = 2, opts=
             if not st.converged and st.rel_res > max_rel_res:
                 raise RuntimeError(f"adaptive step {it}: solve stalled at relative residual {st.rel_res:.3e}")
             U = P.energy(u)
-            _, lay = P.jump_indicator(u, faces="z")
-            side = float(P.jump_indicator(u, faces="side")[1].sum()) if disk else 0.0
+            _, lay = P.jump_indicator(u, faces="z", weight=weight)
+            side = float(P.jump_indicator(u, faces="side", weight=weight)[1].sum()) if disk else 0.0
             n_dof = int(P.info.n_dof)
         finally:
             P.close()

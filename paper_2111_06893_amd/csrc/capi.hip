@@ -455,7 +455,10 @@ dgtn_status dgtn_material_constants(const dgtn_material* m, double* out) {
 dgtn_status dgtn_jump_indicator(dgtn_ctx* c, const double* u, int faces, double* eta_elem, double* eta_layers,
                                 hipStream_t s) {
     if (!c || !u || (!eta_elem && !eta_layers)) { set_error("null argument"); return DGTN_EINVAL; }
-    if (faces < DGTN_FACES_SIDE || faces > DGTN_FACES_ALL) { set_error("faces must be 1, 2 or 3"); return DGTN_EINVAL; }
+    if ((faces & DGTN_FACES_ALL) == 0 || (faces & ~(DGTN_FACES_ALL | DGTN_FACES_PENALTY)) != 0) {
+        set_error("faces must be 1, 2 or 3, optionally or-ed with DGTN_FACES_PENALTY (4)");
+        return DGTN_EINVAL;
+    }
     if (!c->bound) { set_error("no workspace bound"); return DGTN_EINVAL; }
     const Level& L = c->levels[0];
     auto v = view_of<double>(c, L);

@@ -274,8 +274,10 @@ __global__ __launch_bounds__(threads_for<N>()) void k_energy_grad(LevelView<doub
 // quadrature of the operator (w_face J^Sigma).  The jump is what the interior
 // penalty of eq. penalty acts on; Sec. 4 names adaptive refinement as the next
 // step.  The sum may be restricted to the side faces or to the z-faces, where
-// refinement across the layers acts.  One workgroup per element: wave 0
-// resolves the face records, one lane per face node, a fixed-order sum.
+// refinement across the layers acts, and each term may be weighted by the
+// penalty sigma at its node (the jump part of the DG energy norm).  One
+// workgroup per element: wave 0 resolves the face records, one lane per face
+// node, a fixed-order sum.
 template <int N>
 __global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<double> L,
                                                                      const double* __restrict__ u, int which,
@@ -290,7 +292,8 @@ __global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<
     if (tid < 64) load_faces<N>(L, col, iz, tid, sface, sown);
     __syncthreads();
     double dens = 0;
-    // which: 1 the side faces (logical xi, eta), 2 the z-faces (zeta), 3 both
+    // which: 1 the side faces (logical xi, eta), 2 the z-faces (zeta), 3 both;
+    // bit 4: weighted by the penalty sigma
     if (tid < 6 * N2 && (which & (tid / N2 < 4 ? 1 : 2))) {
         const int f = tid / N2, fi = tid % N2;
         int i, j, k;
@@ -322,6 +325,7 @@ __global__ __launch_bounds__(line_threads<N>()) void k_jump_indicator(LevelView<
             for (int c = 0; c < 3; ++c) s2 += ue[c * N3] * ue[c * N3];
             dens = ws * s2;
         }
+        if (which & 4) dens *= f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? j : i)] : fo.sig;
     }
     for (int off = 32; off > 0; off >>= 1) dens += __shfl_xor(dens, off);
     if (lane == 0) red[wave] = dens;

@@ -4,7 +4,9 @@ substrate of one element, p = 2, Gaussian load).  The z-face jumps sit in the
 substrate, the loop refines it, and the energy converges to that of the same
 mesh refined sixteen times in z in every layer (the reference removes the z
 error only, the resolution across the disk being the same).  Observed per-step
-ratios: energy error 0.32, 0.23, 0.16; indicator 0.07, 0.17, 0.19.  At about the
+ratios: energy error 0.32, 0.23, 0.16; indicator (weighted by the penalty, the
+loop's default) 0.19, 0.37, 0.33, against 0.07, 0.17, 0.19 unweighted: sigma ~ 1/h
+takes one power of h from its rate.  At about the
 same number of unknowns, refining every layer four times over is several times
 less accurate (1.2e-2 against 1.9e-3)."""
 import numpy as np
@@ -47,7 +49,7 @@ def test_adaptive_z_refinement_converges_to_the_z_refined_energy():
     tot = [st.eta_layers.sum() for st in steps]
     assert steps[0].marked == [1]                     # the one-element substrate carries the jumps
     assert all(b < 0.5 * a for a, b in zip(err, err[1:])), err
-    assert all(b < 0.3 * a for a, b in zip(tot, tot[1:])), tot
+    assert all(b < 0.5 * a for a, b in zip(tot, tot[1:])), tot
     for a, b in zip(steps, steps[1:]):                # each mesh is the last one with its marked layers doubled
         assert [l["n_elem"] for l in b.spec["layers"]] == \
             [l["n_elem"] * (2 if k in a.marked else 1) for k, l in enumerate(a.spec["layers"])]

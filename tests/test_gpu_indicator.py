@@ -1,7 +1,8 @@
 """GPU parity of the face-jump indicator (dgtn_jump_indicator) with the oracle's
 (oracle/indicator.py, pinned in tests/test_oracle_indicator.py): every element's
 value and the per-layer sums on the same seeded fields, over all faces, the
-side faces and the z-faces, FP64 to 1e-12 of the largest value; boxes at p = 1, 3, 7 (Dirichlet, pressure and free faces), the
+side faces and the z-faces, plain and weighted by the penalty, FP64 to 1e-12
+of the largest value; boxes at p = 1, 3, 7 (Dirichlet, pressure and free faces), the
 curved cylinder, and the thin-coating workload at full size."""
 import numpy as np
 import pytest
@@ -33,11 +34,12 @@ def test_indicator_matches_oracle(name):
     P = dgtn.Problem(spec)
     O = dg.Problem(spec)
     ud = torch.from_numpy(u).to("cuda")
-    for faces in ("all", "side", "z"):
-        eta, lay = P.jump_indicator(ud, faces)
-        ref = indicator.jump_indicator(O, u, faces)
-        assert np.abs(eta - ref).max() <= 1e-12 * np.abs(ref).max(), faces
-        np.testing.assert_allclose(lay, indicator.layer_indicator(O, u, faces), rtol=1e-12)
+    for weight in ("jump", "penalty"):
+        for faces in ("all", "side", "z"):
+            eta, lay = P.jump_indicator(ud, faces, weight)
+            ref = indicator.jump_indicator(O, u, faces, weight)
+            assert np.abs(eta - ref).max() <= 1e-12 * np.abs(ref).max(), (faces, weight)
+            np.testing.assert_allclose(lay, indicator.layer_indicator(O, u, faces, weight), rtol=1e-12)
 
 
 def test_indicator_of_a_linear_field_is_the_fixed_face_integral():
@@ -63,7 +65,7 @@ def test_indicator_rejects_bad_arguments():
     P.jump_indicator(u)      # binds the workspace
     eta = np.zeros(P.info.n_elem)
     dp = ctypes.POINTER(ctypes.c_double)
-    for faces in (0, 4, -1):
+    for faces in (0, 4, 8, 11, -1):
         st = P.lib.dgtn_jump_indicator(P.ctx, ctypes.c_void_p(u.data_ptr()), faces, eta.ctypes.data_as(dp), None,
                                        P._stream())
         assert st == -1, (faces, st)                  # DGTN_EINVAL

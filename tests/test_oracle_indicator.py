@@ -11,6 +11,8 @@
   sides of every face (shared face nodes), so the interior part is zero there too,
   and a constant field gives c^2 times the area of the fixed face, pi R^2 up to
   the geometric approximation of the circle.
+* Weighted by the penalty sigma = C (p + 1)^2 / min(h, h'), the same steps give
+  sigma times those integrals, with the widths of the box's elements.
 """
 import numpy as np
 import pytest
@@ -112,3 +114,37 @@ def test_face_families_add_up_and_separate():
     assert wz.sum() == pytest.approx(c * c * 0.5 * spec["Lx"] * spec["Ly"], rel=1e-13)
     H = P.node_xyz()[:, 2].max() - P.node_xyz()[:, 2].min()
     assert indicator.jump_indicator(P, w, "side").sum() == pytest.approx(c * c * spec["Ly"] * H, rel=1e-13)
+
+
+def test_penalty_weight_closed_forms():
+    """weight="penalty": each face's term times sigma = C (p + 1)^2 / min(h, h'),
+    with h the element width normal to the face (h = 2 J / J^Sigma is exactly that
+    width on a box).  Closed forms on the layered box: a step across the layer
+    interface (widths 0.1 above, 0.25 below), a step across the plane x = 0
+    (widths 0.6 on both sides) with its fixed-face part (bottom width 0.25), and
+    the linear field whose only term is the fixed face."""
+    spec = layered_box()
+    P = dg.Problem(spec)
+    k = spec["penalty"] * (spec["p"] + 1) ** 2
+    Lx, Ly = spec["Lx"], spec["Ly"]
+    H = 0.6
+    c = 0.7
+    v = np.zeros(P.shape)
+    v[P.mesh.layer == 0, 1] = c
+    assert indicator.jump_indicator(P, v, "z", "penalty").sum() == pytest.approx(k / 0.1 * c * c * Lx * Ly, rel=1e-13)
+    np.testing.assert_allclose(indicator.layer_indicator(P, v, "all", "penalty"),
+                               [0.5 * k / 0.1 * c * c * Lx * Ly] * 2, rtol=1e-13)
+    x = P.node_xyz()[:, 0]
+    w = np.zeros(P.shape)
+    w[x.mean(axis=(1, 2, 3)) > 0, 2] = c
+    assert indicator.jump_indicator(P, w, "side", "penalty").sum() == pytest.approx(k / 0.6 * c * c * Ly * H,
+                                                                                    rel=1e-13)
+    assert indicator.jump_indicator(P, w, "z", "penalty").sum() == pytest.approx(k / 0.25 * c * c * 0.5 * Lx * Ly,
+                                                                                 rel=1e-13)
+    # the linear field: only the fixed face, whose elements are 0.25 wide
+    xyz = P.node_xyz()
+    u = np.stack([0.3 * xyz[:, 0] - 0.5 * xyz[:, 2] + 0.2, 0.9 * xyz[:, 1], 0.1 * xyz[:, 2] - 0.4], axis=1)
+    np.testing.assert_allclose(indicator.jump_indicator(P, u, "all", "penalty"),
+                               k / 0.25 * indicator.jump_indicator(P, u, "all"), rtol=1e-13, atol=1e-15)
+    with pytest.raises(ValueError):
+        indicator.jump_indicator(P, u, "all", "sigma")
