@@ -6,7 +6,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdgtn.so")
+# the in-tree build, or another build of the same sources named by DGTN_LIBRARY
+LIB_PATH = os.environ.get("DGTN_LIBRARY") or os.path.join(HERE, "libdgtn.so")
 HEADER = os.path.join(HERE, "..", "include", "dgtn.h")
 
 c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -97,6 +98,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
                            "(python paper_2111_06893_amd/build.py)")
+    # torch first: it ships its own HIP runtime under the same soname as the
+    # system one the library links, so whichever is loaded first serves both.
+    # Loaded the other way round, torch runs on the system runtime, and the
+    # library's calls then found no device.  Torch's is the one the device
+    # memory and streams come from.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
