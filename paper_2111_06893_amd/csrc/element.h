@@ -48,6 +48,56 @@ __device__ __forceinline__ void sym_outer(const R n[3], const R v[3], R S[6]) {
     S[5] = R(0.5) * (n[1] * v[2] + n[2] * v[1]);
 }
 
+// The same products with the zero components of a face normal left out: a
+// side face's normal has no z-component, a z-face's is (0, 0, s), s = +-1.
+// IEEE arithmetic does not let the compiler drop x * 0 or x + 0 by itself (x
+// could be infinite, or -0), and those terms were about a tenth of the FP64
+// work of the face and node phases.  For finite values the results are the
+// same as the general forms.
+template <typename R>
+__device__ __forceinline__ void traction_xy(R nx, R ny, const R T[6], R t[3]) {
+    t[0] = nx * T[0] + ny * T[3];
+    t[1] = nx * T[3] + ny * T[1];
+    t[2] = nx * T[4] + ny * T[5];
+}
+
+template <typename R>
+__device__ __forceinline__ void traction_z(R s, const R T[6], R t[3]) {
+    t[0] = s * T[4];
+    t[1] = s * T[5];
+    t[2] = s * T[2];
+}
+
+// S += sym(n (x) v), side face and z-face
+template <typename R>
+__device__ __forceinline__ void add_sym_outer_xy(R nx, R ny, const R v[3], R S[6]) {
+    S[0] += nx * v[0];
+    S[1] += ny * v[1];
+    S[3] += R(0.5) * (nx * v[1] + ny * v[0]);
+    S[4] += R(0.5) * (nx * v[2]);
+    S[5] += R(0.5) * (ny * v[2]);
+}
+
+template <typename R>
+__device__ __forceinline__ void add_sym_outer_z(R s, const R v[3], R S[6]) {
+    S[2] += s * v[2];
+    S[4] += R(0.5) * (s * v[0]);
+    S[5] += R(0.5) * (s * v[1]);
+}
+
+// n . Y : sym(n (x) v) for a side-face normal (n_z = 0) and cubic moduli: the
+// penalty traction of a jump v (eq. penalty).  On a z-face it reduces to
+// (c44 v_x, c44 v_y, c11 v_z) whatever the sign of the normal.
+template <typename R>
+__device__ __forceinline__ void penalty_traction_xy(R c11, R c12, R c44, R nx, R ny, const R v[3], R t[3]) {
+    const R S0 = nx * v[0], S1 = ny * v[1];
+    const R S3 = R(0.5) * (nx * v[1] + ny * v[0]);
+    const R S4 = R(0.5) * (nx * v[2]), S5 = R(0.5) * (ny * v[2]);
+    const R T[6] = {c11 * S0 + c12 * S1, c11 * S1 + c12 * S0, R(0), R(2) * c44 * S3, R(2) * c44 * S4,
+                    R(2) * c44 * S5};
+    traction_xy(nx, ny, T, t);
+}
+
 // Per-node geometry of an extruded element.
 template <typename R>
 struct NodeGeo {
@@ -122,6 +172,16 @@ __device__ __forceinline__ void face_frame(const LevelView<R>& L, int col, int f
         n[1] = 0;
         n[2] = (f == 5) ? R(1) : R(-1);
     }
+}
+
+// Outward unit normal (nx, ny, 0) and |grad xi^m| of side face f < 4 at a node.
+template <int N, typename R>
+__device__ __forceinline__ void side_normal(const LevelView<R>& L, int col, int f, int i, int j, R& nx, R& ny,
+                                            R& amag) {
+    const R* t = L.fnrm + ((size_t)col * 4 + f) * 3 * N + (f < 2 ? j : i);
+    nx = t[0];
+    ny = t[N];
+    amag = t[2 * N];
 }
 
 // Flattened index of node (i, j, k) within face f (the face-buffer order).
@@ -289,16 +349,54 @@ constexpr int op_threads() {
 }
 
 // Line task t < 9 N^2: direction d (xi, eta, zeta), component c, and the offset
-// and stride of the line's N nodes within one component's N^3 block.
+// and stride of the line's N nodes within one component's N^3 block, packed
+// into one word per task (base | c << 10 | d << 12 | stride << 14) at compile
+// time.  A lane reads its word with one load instead of decoding t by divisions
+// by constants, about twenty instructions per pass.
 template <int N>
-__device__ __forceinline__ void line_of(int t, int& d, int& c, int& base, int& stride) {
-    constexpr int N2 = N * N;
-    d = t / (3 * N2);
-    const int rem = t % (3 * N2);
-    c = rem / N2;
-    const int q = rem % N2, q1 = q % N, q2 = q / N;
-    base = d == 0 ? q2 * N2 + q1 * N : d == 1 ? q2 * N2 + q1 : q2 * N + q1;
-    stride = d == 0 ? 1 : d == 1 ? N : N2;
+struct LineCodes {
+    int v[9 * N * N];
+    constexpr LineCodes() : v() {
+        constexpr int N2 = N * N;
+        for (int t = 0; t < 9 * N2; ++t) {
+            const int d = t / (3 * N2), rem = t % (3 * N2), c = rem / N2;
+            const int q = rem % N2, q1 = q % N, q2 = q / N;
+            const int base = d == 0 ? q2 * N2 + q1 * N : d == 1 ? q2 * N2 + q1 : q2 * N + q1;
+            const int stride = d == 0 ? 1 : d == 1 ? N : N2;
+            v[t] = base | c << 10 | d << 12 | stride << 14;
+        }
+    }
+};
+
+template <int N>
+__device__ constexpr LineCodes<N> kLineCodes{};
+
+template <int N>
+__device__ __forceinline__ void line_of(int w, int& d, int& c, int& base, int& stride) {
+    static_assert(N * N * N <= 1024, "base takes ten bits");
+    base = w & 1023;
+    c = (w >> 10) & 3;
+    d = (w >> 12) & 3;
+    stride = w >> 14;
+}
+
+// A lane's line tasks t = tid + p NT, p < passes: their code words, loaded at the
+// start of a kernel so that the load is in flight while u is staged.
+template <int N, int NT>
+struct LineTasks {
+    static constexpr int passes = (9 * N * N + NT - 1) / NT;
+    int w[passes];
+};
+
+template <int N, int NT>
+__device__ __forceinline__ LineTasks<N, NT> line_tasks(int tid) {
+    LineTasks<N, NT> r;
+#pragma unroll
+    for (int p = 0; p < LineTasks<N, NT>::passes; ++p) {
+        const int t = tid + p * NT;
+        r.w[p] = kLineCodes<N>.v[t < 9 * N * N ? t : 0];
+    }
+    return r;
 }
 
 // Sum-factorised 1D contraction along one line, one lane per line: the N
@@ -328,12 +426,14 @@ __device__ __forceinline__ void line_contract(const LevelView<R>& L, const R* sr
 // sG[(d * 3 + c) * N^3 + node], from the LDS copy of u.
 // NT lanes take the 9 N^2 lines in passes of NT.
 template <int N, typename R, int NT = line_threads<N>()>
-__device__ __forceinline__ void ref_derivatives(const LevelView<R>& L, const R* su, R* sG, int tid) {
+__device__ __forceinline__ void ref_derivatives(const LevelView<R>& L, const R* su, R* sG, int tid,
+                                                const LineTasks<N, NT>& tasks) {
     constexpr int N3 = N * N * N;
 #pragma unroll
-    for (int t = tid; t < 9 * N * N; t += NT) {
+    for (int p = 0; p < LineTasks<N, NT>::passes; ++p) {
+        if (tid + p * NT >= 9 * N * N) break;
         int d, c, base, stride;
-        line_of<N>(t, d, c, base, stride);
+        line_of<N>(tasks.w[p], d, c, base, stride);
         R* dst = sG + (d * 3 + c) * N3 + base;
         line_contract<N, false>(L, su + c * N3, base, stride, [&](int x, R v) { dst[x * stride] = v; });
     }

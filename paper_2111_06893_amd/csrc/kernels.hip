@@ -33,6 +33,7 @@ __global__ __launch_bounds__(op_threads<N>()) void k_traction(LevelView<R> L, co
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
+    const LineTasks<N, NT> tasks = line_tasks<N, NT>(tid);
     // waves 1.. stage u while wave 0 reads the element's material (two dependent
     // table reads), so that the two latencies overlap instead of adding up
     if (tid >= 64) {
@@ -51,15 +52,20 @@ __global__ __launch_bounds__(op_threads<N>()) void k_traction(LevelView<R> L, co
     if (act) face_node<N>(f, fi, i, j, k);
     NodeGeo<R> g = act ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
     __syncthreads();
-    ref_derivatives<N, R, NT>(L, su, sG, tid);
+    ref_derivatives<N, R, NT>(L, su, sG, tid, tasks);
     __syncthreads();
     if (!act) return;
-    R G[3][3], S[6], T[6], n[3], amag, t[3];
+    R G[3][3], S[6], T[6], t[3];
     node_gradient<N>(sG, k * N2 + j * N + i, g, sown[4], G);
     sym_of(G, S);
     cubic_stress(sown[0], sown[1], sown[2], S, T);
-    face_frame<N>(L, col, f, i, j, n, amag);
-    traction(n, T, t);
+    if (f < 4) {
+        R nx, ny, amag;
+        side_normal<N>(L, col, f, i, j, nx, ny, amag);
+        traction_xy(nx, ny, T, t);
+    } else {
+        traction_z(f == 5 ? R(1) : R(-1), T, t);
+    }
     R* dst = tau + ((size_t)e * 6 + f) * 3 * N2 + fi;
     dst[0] = t[0];
     dst[N2] = t[1];
@@ -101,15 +107,18 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
-    // waves 1.. stage u and the weights (threads past N store the last weight
-    // again) while wave 0 resolves the face records, whose table reads depend on
-    // one another: the two latencies overlap instead of adding up
+    const LineTasks<N, NT> tasks = line_tasks<N, NT>(tid);
+    // waves 1.. stage u and the weights while wave 0 resolves the face records,
+    // whose table reads depend on one another: the two latencies overlap instead
+    // of adding up
     if (tid >= 64) {
         const int t = tid - 64;
         const R wq = L.w[min(t, N - 1)];
         stage_to_lds<3 * N3, NT - 64>(su, ue, t);
-        sw[min(t, N - 1)] = wq;
-        swi[min(t, N - 1)] = R(1) / wq;
+        if (t < N) {  // one wave divides
+            sw[t] = wq;
+            swi[t] = R(1) / wq;
+        }
     } else {
         load_faces<N>(L, col, iz, tid, sface, sown);
     }
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
     }
     const R c11 = sown[0], c12 = sown[1], c44 = sown[2];
     // 1. line lanes: reference derivatives of u
-    ref_derivatives<N, R, NT>(L, su, sG, tid);
+    ref_derivatives<N, R, NT>(L, su, sG, tid, tasks);
     __syncthreads();
     // 2. node lanes: unlifted gradient and stress; interior traction on each face slot.
     // Only this lane reads its node's derivatives, so S is parked in those slots.
@@ -170,9 +179,14 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 if (faces[q] < 0) continue;
-                R n[3], amag, t[3];
-                face_frame<N>(L, col, faces[q], i, j, n, amag);
-                traction(n, T, t);
+                R t[3];
+                if (q < 2) {
+                    R nx, ny, amag;
+                    side_normal<N>(L, col, faces[q], i, j, nx, ny, amag);
+                    traction_xy(nx, ny, T, t);
+                } else {
+                    traction_z(faces[q] == 5 ? R(1) : R(-1), T, t);
+                }
                 const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
                 sFT[slot] = t[0];
                 sFT[slot + N2] = t[1];
@@ -188,31 +202,32 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
         const R det2 = L.geo2[(size_t)col * 5 * N2 + 4 * N2 + fi_j * N + fi_i];
         const R hz = sown[3];
         const FaceInfo<R>& fo = sface[f];  // read from LDS where used
-        const R sigma = f < 4 ? L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)] : fo.sig;
-        R n[3], amag;
-        face_frame<N>(L, col, f, fi_i, fi_j, n, amag);
-        R wsig, lr;
-        if (f >= 4) {
-            wsig = sw[fi_i] * sw[fi_j] * det2;
-            lr = swi[fi_k] * sown[4];
-        } else if (f < 2) {
-            wsig = sw[fi_j] * sw[fi_k] * R(0.5) * hz * det2 * amag;
-            lr = amag * swi[fi_i];
-        } else {
-            wsig = sw[fi_i] * sw[fi_k] * R(0.5) * hz * det2 * amag;
-            lr = amag * swi[fi_j];
-        }
         const int qn = fi_k * N2 + fi_j * N + fi_i;
         const int slot = f * 3 * N2 + fi;
-        R jump[3] = {0, 0, 0}, flux[3] = {0, 0, 0};
-        if (fo.bc == 0 || fo.bc == DGTN_BC_DIRICHLET) {
-            const bool interior = fo.bc == 0;
+        const bool interior = fo.bc == 0, penalised = interior || fo.bc == DGTN_BC_DIRICHLET;
+        R jump[3] = {0, 0, 0}, flux[3] = {0, 0, 0}, pen[3] = {0, 0, 0};
+        if (penalised) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) jump[c] = interior ? su[c * N3 + qn] - un[c] : R(2) * su[c * N3 + qn];
-            R Sj[6], Tj[6], pen[3];
-            sym_outer(n, jump, Sj);
-            cubic_stress(fo.c11, fo.c12, fo.c44, Sj, Tj);
-            traction(n, Tj, pen);
+        }
+        // sigma n . Y* : sym(n (x) [u]) by face family (the z-faces' normal has one component)
+        R wsig, lr, sigma;
+        if (f < 4) {
+            R nx, ny, amag;
+            side_normal<N>(L, col, f, fi_i, fi_j, nx, ny, amag);
+            sigma = L.sig_side[((size_t)col * 4 + f) * N + (f < 2 ? fi_j : fi_i)];
+            wsig = sw[f < 2 ? fi_j : fi_i] * sw[fi_k] * R(0.5) * hz * det2 * amag;
+            lr = amag * swi[f < 2 ? fi_i : fi_j];
+            if (penalised) penalty_traction_xy(fo.c11, fo.c12, fo.c44, nx, ny, jump, pen);
+        } else {
+            sigma = fo.sig;
+            wsig = sw[fi_i] * sw[fi_j] * det2;
+            lr = swi[fi_k] * sown[4];
+            pen[0] = fo.c44 * jump[0];
+            pen[1] = fo.c44 * jump[1];
+            pen[2] = fo.c11 * jump[2];
+        }
+        if (penalised) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const R tint = sFT[slot + c * N2];
@@ -243,13 +258,16 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
         for (int q = 0; q < 3; ++q) {
             if (faces[q] < 0) continue;
             const int slot = faces[q] * 3 * N2 + face_index<N>(faces[q], i, j, k);
-            R n[3], amag, lj[3], Sl[6];
-            face_frame<N>(L, col, faces[q], i, j, n, amag);
+            R lj[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) lj[c] = sLF[slot + c * N2];
-            sym_outer(n, lj, Sl);
-#pragma unroll
-            for (int s = 0; s < 6; ++s) S[s] += Sl[s];
+            if (q < 2) {
+                R nx, ny, amag;
+                side_normal<N>(L, col, faces[q], i, j, nx, ny, amag);
+                add_sym_outer_xy(nx, ny, lj, S);
+            } else {
+                add_sym_outer_z(faces[q] == 5 ? R(1) : R(-1), lj, S);
+            }
         }
         R T[6];
         cubic_stress(c11, c12, c44, S, T);
@@ -270,9 +288,10 @@ __global__ __launch_bounds__(op_threads<N>(), (apply_waves<N, R>())) void k_appl
     // 5. weak divergence sum_m D_m^T F^m, one lane per line: F^m_c along a line is
     // read by that line's lane only, so each lane overwrites its line in place
 #pragma unroll
-    for (int t = tid; t < 9 * N2; t += NT) {
+    for (int p = 0; p < LineTasks<N, NT>::passes; ++p) {
+        if (tid + p * NT >= 9 * N2) break;
         int d, c, base, stride;
-        line_of<N>(t, d, c, base, stride);
+        line_of<N>(tasks.w[p], d, c, base, stride);
         R* line = sG + (d * 3 + c) * N3 + base;
         R v[N];
 #pragma unroll
