@@ -600,7 +600,8 @@ def main():
     del P, u64, o64
     torch.cuda.empty_cache()
     if not args.no_extra:
-        out["thin_coating"] = thin_coating(log, args.reps)
+        out["thin_coating"] = secondary("thin_coating", log, args.reps)
+        out["forty_layer_p6"] = secondary("forty_layer_p6", log, args.reps)
         out["hbm_sweep"] = hbm_sweep(log, args.reps)
         out["seeded_beams"] = seeded_beams(log)
         out["design_loop"] = design_loop(log)
@@ -611,16 +612,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def thin_coating(log, reps):
-    """The thin-coating cylinder: apply rates, kernel rooflines and time-to-U."""
+def secondary(name, log, reps):
+    """A secondary workload (the thin-coating cylinder, the forty-layer coating
+    at p = 6): apply rates, kernel rooflines and time-to-U."""
     import torch
     import paper_2111_06893_amd as dgtn
-    P = dgtn.Problem(workload("thin_coating"))
+    P = dgtn.Problem(workload(name))
     P.bind(dgtn.default_opts(32))
-    rec = apply_record("thin_coating", P, reps, 5, torch.cuda.current_stream())
+    rec = apply_record(name, P, reps, 5, torch.cuda.current_stream())
     rec["time_to_U"] = time_to_u(P, log=log)
     P.close()
-    log(f"thin coating: apply {rec['apply_fp64_dof_per_s']:.3e} DoF/s")
+    torch.cuda.empty_cache()
+    log(f"{name}: apply {rec['apply_fp64_dof_per_s']:.3e} DoF/s")
     return rec
 
 
