@@ -410,7 +410,7 @@ template <> struct MfmaAcc<float> {
     __device__ static int row(int lane, int q) { return 4 * (lane / 16) + q; }
 };
 
-constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
+constexpr int kGK = 32, kGPad = 4;
 // W: patch width (the eigenvalue division splits the column index by W and W^2,
 // compile-time constants here); div = 0 takes W = 0.
 // waves per SIMD asked of the compiler: five in FP32 (96 registers; four would
@@ -420,19 +420,24 @@ constexpr int gemm_waves() {
     return sizeof(R) == 4 ? 5 : 3;
 }
 
-template <typename R, int W, int div>
+// T: the workgroup's output tile, T x T (64, or 32 on the small coarse levels,
+// whose 64 x 64 grids would leave most compute units idle: measured at M = K =
+// 200 and 1280 / 320 columns, 11.7 -> 10.7 and 11.1 -> 5.7 us); each of the four
+// waves takes a (T/2) x (T/2) quarter in 16 x 16 MFMA blocks.
+template <typename R, int W, int div, int T>
 __global__ __launch_bounds__(256, gemm_waves<R>()) void k_col_gemm_mfma(int n, int ncol, const R* __restrict__ A,
                                                        const R* __restrict__ in, R* __restrict__ out,
                                                        const R* __restrict__ lz, const R* __restrict__ lam,
                                                        const R* __restrict__ rat) {
     using Acc = MfmaAcc<R>;
+    constexpr int kGM = T, kGN = T, BL = T / 32;  // BL x BL blocks per wave
     constexpr int LA = kGK * kGM / 256, LB = kGK * kGN / 256;  // staged values per thread
     __shared__ R As[kGK][kGM + kGPad];  // As[k][row]
     __shared__ R Bs[kGK][kGN + kGPad];  // Bs[k][col]
     const int c = blockIdx.z;
     const int row0 = blockIdx.y * kGM, col0 = blockIdx.x * kGN;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
+    const int wr = (wave / 2) * (T / 2), wc = (wave % 2) * (T / 2);
     const R* Ac = A + (size_t)c * n * n;
     const R* Bc = in + (size_t)c * n * ncol;
     // the next K chunk is fetched into registers while the current one is
@@ -458,21 +463,21 @@ __global__ __launch_bounds__(256, gemm_waves<R>()) void k_col_gemm_mfma(int n, i
             vb[t] = kg < n && cg < ncol;
         }
     };
-    typename Acc::type acc[2][2];
+    typename Acc::type acc[BL][BL];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BL; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
+        for (int b = 0; b < BL; ++b) acc[a][b] = typename Acc::type{0, 0, 0, 0};
     fetch(0);
     // in-plane part of the denominators of this lane's outputs, whose table reads
     // depend on one another, fetched before the K loop (indices clamped: outputs
     // past n or ncol are computed but not stored); the z-eigenvalues, single
     // loads, are read after it, which keeps the registers at five waves per SIMD
-    R lxy[2];
+    R lxy[BL];
     if constexpr (div) {
         constexpr int W2 = W * W;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BL; ++b) {
             const int cg = min(col0 + wc + 16 * b + lane % 16, ncol - 1);
             const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
             lxy[b] = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
@@ -493,32 +498,32 @@ __global__ __launch_bounds__(256, gemm_waves<R>()) void k_col_gemm_mfma(int n, i
         __syncthreads();
         if (k0 + kGK < n) fetch(k0 + kGK);
         // fragments of the next K step read from LDS while this step's products run
-        R af[2][2], bf[2][2];
+        R af[2][BL], bf[2][BL];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) af[0][a] = As[lane / 16][wr + 16 * a + lane % 16];
+        for (int a = 0; a < BL; ++a) af[0][a] = As[lane / 16][wr + 16 * a + lane % 16];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bf[0][b] = Bs[lane / 16][wc + 16 * b + lane % 16];
+        for (int b = 0; b < BL; ++b) bf[0][b] = Bs[lane / 16][wc + 16 * b + lane % 16];
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
             const int cur = (ks / 4) & 1, nx = cur ^ 1;
             if (ks + 4 < kGK) {
 #pragma unroll
-                for (int a = 0; a < 2; ++a) af[nx][a] = As[ks + 4 + lane / 16][wr + 16 * a + lane % 16];
+                for (int a = 0; a < BL; ++a) af[nx][a] = As[ks + 4 + lane / 16][wr + 16 * a + lane % 16];
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bf[nx][b] = Bs[ks + 4 + lane / 16][wc + 16 * b + lane % 16];
+                for (int b = 0; b < BL; ++b) bf[nx][b] = Bs[ks + 4 + lane / 16][wc + 16 * b + lane % 16];
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < BL; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = Acc::step(af[cur][a], bf[cur][b], acc[a][b]);
+                for (int b = 0; b < BL; ++b) acc[a][b] = Acc::step(af[cur][a], bf[cur][b], acc[a][b]);
         }
         __syncthreads();
     }
     R* Oc = out + (size_t)c * n * ncol;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BL; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BL; ++b) {
             const int cg = col0 + wc + 16 * b + lane % 16;
             if (cg >= ncol) continue;
 #pragma unroll
@@ -1083,14 +1088,16 @@ hipError_t dispatch(int N, F&& f) {
 
 // Both z-products of one smoother application: Y = (V^T T) / (lz + lxy), then T = V Y.
 // V [2][3][n][n] holds the eigenvectors and, after them, their transposes.
-template <typename R>
-hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
-                         hipStream_t s) {
-    const dim3 grid((ncol + kGN - 1) / kGN, (n + kGM - 1) / kGM, 3);
+// 64 x 64 output tiles unless their grid would have fewer workgroups than
+// gfx950 has compute units (256); then 32 x 32.
+template <typename R, int TT>
+hipError_t col_gemm_pair_t(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
+                           hipStream_t s) {
+    const dim3 grid((ncol + TT - 1) / TT, (n + TT - 1) / TT, 3);
     hipError_t err = hipErrorInvalidValue;
     auto fwd = [&](auto w) {
         constexpr int WW = decltype(w)::value;
-        hipLaunchKernelGGL((k_col_gemm_mfma<R, WW, 1>), grid, dim3(256), 0, s, n, ncol, V, T, Y, lz, lam, rat);
+        hipLaunchKernelGGL((k_col_gemm_mfma<R, WW, 1, TT>), grid, dim3(256), 0, s, n, ncol, V, T, Y, lz, lam, rat);
         return hipGetLastError();
     };
     switch (W) {
@@ -1110,9 +1117,18 @@ hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R
         default: break;
     }
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_col_gemm_mfma<R, 0, 0>), grid, dim3(256), 0, s, n, ncol, V + (size_t)3 * n * n, Y, T, lz,
-                       lam, rat);
+    hipLaunchKernelGGL((k_col_gemm_mfma<R, 0, 0, TT>), grid, dim3(256), 0, s, n, ncol, V + (size_t)3 * n * n, Y, T,
+                       lz, lam, rat);
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
+                         hipStream_t s) {
+    constexpr long kComputeUnits = 256;
+    const long tiles64 = 3L * ((ncol + 63) / 64) * ((n + 63) / 64);
+    return tiles64 < kComputeUnits ? col_gemm_pair_t<R, 32>(W, n, ncol, V, T, Y, lz, lam, rat, s)
+                                   : col_gemm_pair_t<R, 64>(W, n, ncol, V, T, Y, lz, lam, rat, s);
 }
 
 // (Nf, Nc) pairs of the p-coarsening as compile-time constants; other pairs run
