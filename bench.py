@@ -605,6 +605,7 @@ def main():
         out["hbm_sweep"] = hbm_sweep(log, args.reps)
         out["seeded_beams"] = seeded_beams(log)
         out["design_loop"] = design_loop(log)
+        out["design_mirror"] = design_mirror(log)
         out["adaptive_refinement"] = adaptive_refinement(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(HEADLINE, args.cpu_budget, ttu_proc, log)
@@ -693,6 +694,46 @@ def design_loop(log):
     return {"workload": "beam centre on xc - yc = 0.2 minimising S_x, five-block cylinder, 40 elements, p=5",
             "x": r.x.tolist(), "expected": [0.1, -0.1], "evaluations": r.n_evals, "seconds": dt,
             "S_x": r.fun}
+
+
+def design_mirror(log, maxiter=30):
+    """Untimed record of the design loop on the forty-layer mirror: S_x (loss
+    angles 1e-4 on crystal A, 1e-5 on crystal B, 1e-7 on the substrate:
+    synthetic) minimised over the forty coating thicknesses, with their sum held
+    at its nominal 4e-4 R and each within [0.5, 1.5] of its nominal 1e-5 R.  A
+    coating layer's energy is close to proportional to its thickness, so the
+    problem is close to a linear programme, whose optimum puts the layers of
+    lower phi times energy per thickness at the upper bound and the others at
+    the lower.  Every evaluation is a mesh and hierarchy set-up, a forward and
+    an adjoint solve and the forty thickness derivatives."""
+    import torch
+    import paper_2111_06893_amd as dgtn
+    from paper_2111_06893_amd import design
+    spec = workload(HEADLINE)
+    n = len(spec["layers"]) - 1
+    phi = np.r_[[1e-4 if spec["layers"][k]["material"] == 1 else 1e-5 for k in range(n)], 1e-7]
+    d0 = np.array([spec["layers"][k]["thickness"] for k in range(n)])
+    opts = dgtn.default_opts(32, rtol=5e-8, max_iter=2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = design.optimize(spec, [("thickness", k) for k in range(n)], design.NoiseObjective(phi, 300.0, 100.0),
+                        constraints=[design.fixed_sum(range(n), float(d0.sum()))],
+                        bounds=[(0.5 * d, 1.5 * d) for d in d0], tol=1e-9, maxiter=maxiter,
+                        engine=design.device_engine(opts, max_rel_res=1e-5))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ratio = r.x / d0
+    low_phi = np.array([phi[k] < 1e-4 for k in range(n)])
+    S0 = r.history[0][1]
+    log(f"mirror design: S_x {S0:.4e} -> {r.fun:.4e} in {r.n_evals} evaluations, {dt:.1f} s")
+    return {"workload": "forty-layer mirror: S_x over the forty coating thicknesses at fixed total thickness, "
+                        "each in [0.5, 1.5] x 1e-5 R; loss angles 1e-4 (crystal A), 1e-5 (crystal B), 1e-7 "
+                        "(substrate), synthetic",
+            "S_x_start": S0, "S_x_end": r.fun, "evaluations": r.n_evals, "seconds": dt,
+            "success": r.success, "message": r.message,
+            "thickness_ratio_low_phi_layers": [float(ratio[low_phi].min()), float(ratio[low_phi].max())],
+            "thickness_ratio_high_phi_layers": [float(ratio[~low_phi].min()), float(ratio[~low_phi].max())],
+            "total_thickness_rel_change": float(r.x.sum() / d0.sum() - 1.0)}
 
 
 def adaptive_refinement(log, steps=3):

@@ -8,6 +8,13 @@
 * Identification: the coating's Young's modulus and the beam width of the
   coated cylinder recovered from the two layer energies they produce, from a
   start 15-20 % off.
+* The forty-layer mirror: S_x (loss angles 1e-4 on crystal A, 1e-5 on crystal
+  B) over the forty coating thicknesses at fixed total thickness, each within
+  [0.5, 1.5] of nominal.  A thin layer's energy is nearly proportional to its
+  thickness, so the problem is nearly a linear programme: every B layer ends at
+  the upper bound, every A layer at the lower, the total unchanged, and at that
+  point the KKT conditions hold: each A layer's derivative of S_x exceeds each
+  B layer's (moving thickness from A to B would still lower S_x).
 """
 import numpy as np
 import pytest
@@ -49,3 +56,23 @@ def test_identify_coating_modulus_and_beam_width():
                         bounds=[(0.3 * truth[0], 3 * truth[0]), (0.05, 0.4)], tol=1e-14, maxiter=60)
     print("identify", r.x / truth - 1, r.n_evals, r.message)
     np.testing.assert_allclose(r.x, truth, rtol=1e-5)
+
+
+def test_forty_layer_mirror_thicknesses():
+    print("[design] forty-layer mirror", flush=True)
+    spec = W.config5(p=5)
+    n = len(spec["layers"]) - 1
+    is_a = np.array([spec["layers"][k]["material"] == 1 for k in range(n)])
+    phi = np.r_[np.where(is_a, 1e-4, 1e-5), 1e-7]
+    d0 = np.array([spec["layers"][k]["thickness"] for k in range(n)])
+    r = design.optimize(spec, [("thickness", k) for k in range(n)], design.NoiseObjective(phi, 300.0, 100.0),
+                        constraints=[design.fixed_sum(range(n), float(d0.sum()))],
+                        bounds=[(0.5 * d, 1.5 * d) for d in d0], tol=1e-9, maxiter=30,
+                        engine=design.device_engine(dgtn.default_opts(32, rtol=5e-8, max_iter=2000),
+                                                    max_rel_res=1e-5))
+    assert r.success, r.message
+    np.testing.assert_allclose(r.x[~is_a], 1.5 * d0[~is_a], rtol=1e-9)
+    np.testing.assert_allclose(r.x[is_a], 0.5 * d0[is_a], rtol=1e-9)
+    assert abs(r.x.sum() / d0.sum() - 1.0) < 1e-12
+    assert r.grad[is_a].min() > r.grad[~is_a].max()
+    assert r.fun < 0.8 * r.history[0][1]          # observed 3.125e-40 -> 2.368e-40
