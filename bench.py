@@ -713,9 +713,7 @@ def design_mirror(log, maxiter=30):
     n = len(spec["layers"]) - 1
     phi = np.r_[[1e-4 if spec["layers"][k]["material"] == 1 else 1e-5 for k in range(n)], 1e-7]
     d0 = np.array([spec["layers"][k]["thickness"] for k in range(n)])
-    # the adjoint load of these weights sits on the thin layers: the FP32 preconditioner
-    # stalls on it near 2e-6 after some 220 iterations, the FP64 one converges in 12
-    opts = dgtn.default_opts(64, rtol=5e-8, max_iter=2000)
+    opts = dgtn.default_opts(32, rtol=5e-8, max_iter=2000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = design.optimize(spec, [("thickness", k) for k in range(n)], design.NoiseObjective(phi, 300.0, 100.0),

@@ -55,16 +55,16 @@ hipError_t vec_scale_copy(const double* x, double* y, double a, size_t n, hipStr
 hipError_t vec_axpy(double* y, double a, const double* x, size_t n, hipStream_t s);
 hipError_t vec_xpby(double* p, const double* z, double beta, size_t n, hipStream_t s);
 // flexible-CG vector steps reading their scalars from device memory; r32, if
-// not null, receives the new residual in FP32
+// not null, receives the new residual times scale32 (a power of two) in FP32
 hipError_t fcg_update(double* u, double* r, const double* p, const double* q, const double* cur, double* sc,
-                      float* r32, size_t n, hipStream_t s);
+                      float* r32, double scale32, size_t n, hipStream_t s);
 hipError_t fcg_direction(double* p, const double* z, const double* cur, const double* nxt, size_t n,
                          hipStream_t s);
 // out[v] = x[v] . y[v] for v < np <= 4 (deterministic order)
 hipError_t vec_dotpairs(int np, const double* const* x, const double* const* y, size_t n, double* partial, int nblk,
                         double* out, hipStream_t s);
-// zn = (double) z32, then out[0..2] = r . zn, r . zo, r . r (as vec_dotpairs with those pairs)
-hipError_t vec_dot3_widen(const double* r, const float* z32, double* zn, const double* zo, size_t n, double* partial,
-                          int nblk, double* out, hipStream_t s);
+// zn = unscale * (double) z32, then out[0..2] = r . zn, r . zo, r . r (as vec_dotpairs with those pairs)
+hipError_t vec_dot3_widen(const double* r, const float* z32, double* zn, const double* zo, double unscale, size_t n,
+                          double* partial, int nblk, double* out, hipStream_t s);
 
 }  // namespace dgtn

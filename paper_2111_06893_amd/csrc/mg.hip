@@ -946,7 +946,7 @@ __global__ __launch_bounds__(kDotThreads) void k_reduce_partials(const double* _
 // input, written here instead of by a separate pass).
 __global__ void k_fcg_update(double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
                              const double* __restrict__ q, const double* __restrict__ cur,
-                             double* __restrict__ sc, float* __restrict__ r32, size_t n) {
+                             double* __restrict__ sc, float* __restrict__ r32, double scale32, size_t n) {
     const double pq = sc[0];
     const bool ok = pq > 0;
     const double alpha = ok ? cur[0] / pq : 0.0;
@@ -956,7 +956,7 @@ __global__ void k_fcg_update(double* __restrict__ u, double* __restrict__ r, con
     u[t] += alpha * p[t];
     const double rn = r[t] - alpha * q[t];
     r[t] = rn;
-    if (r32) r32[t] = (float)rn;
+    if (r32) r32[t] = (float)(scale32 * rn);  // a power of two: keeps the FP32 input in range
 }
 
 // p = z + beta p, beta = (nxt[0] - nxt[1]) / cur[0]  (Polak-Ribiere)
@@ -1034,13 +1034,13 @@ __global__ __launch_bounds__(kDotThreads) void k_dotpairs(DotPairs d, size_t n, 
 }
 
 // The three dot products of a flexible-CG step with an FP32 preconditioner:
-// zn = (double) z32 is written here (the widening pass folded in), and
+// zn = unscale * (double) z32 is written here (the widening pass folded in), and
 // partial[0..2][blk] = r.zn, r.zo, r.r over the block's slice, in the order
 // and with the reductions of k_dotpairs<3>.
 __global__ __launch_bounds__(kDotThreads) void k_dot3_widen(const double* __restrict__ r,
                                                             const float* __restrict__ z32, double* __restrict__ zn,
-                                                            const double* __restrict__ zo, size_t n,
-                                                            double* __restrict__ partial, int nblk) {
+                                                            const double* __restrict__ zo, double unscale,
+                                                            size_t n, double* __restrict__ partial, int nblk) {
     constexpr int NW = kDotThreads / 64;
     __shared__ double red[3][NW];
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(kDotThreads) void k_dot3_widen(const double* __rest
     double acc[3] = {0, 0, 0};
 #pragma unroll 4
     for (size_t q = lo + tid; q < hi; q += kDotThreads) {
-        const double rq = r[q], z = (double)z32[q];
+        const double rq = r[q], z = unscale * (double)z32[q];
         zn[q] = z;
         acc[0] += rq * z;
         acc[1] += rq * zo[q];
@@ -1335,14 +1335,15 @@ hipError_t vec_multidot(const double* V, size_t ldv, int nv, const double* w, si
 }
 
 hipError_t fcg_update(double* u, double* r, const double* p, const double* q, const double* cur, double* sc,
-                      float* r32, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, r, p, q, cur, sc, r32, n);
+                      float* r32, double scale32, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, r, p, q, cur, sc, r32, scale32,
+                       n);
     return hipGetLastError();
 }
 
-hipError_t vec_dot3_widen(const double* r, const float* z32, double* zn, const double* zo, size_t n, double* partial,
-                          int nblk, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot3_widen, dim3(nblk), dim3(kDotThreads), 0, s, r, z32, zn, zo, n, partial, nblk);
+hipError_t vec_dot3_widen(const double* r, const float* z32, double* zn, const double* zo, double unscale, size_t n,
+                          double* partial, int nblk, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot3_widen, dim3(nblk), dim3(kDotThreads), 0, s, r, z32, zn, zo, unscale, n, partial, nblk);
     hipLaunchKernelGGL(k_reduce_partials, dim3(3), dim3(kDotThreads), 0, s, partial, nblk, out);
     return hipGetLastError();
 }

@@ -1183,8 +1183,24 @@ dgtn_status vcycle_launch(dgtn_ctx* c, int prec, const VOpts& o, hipStream_t s) 
     return DGTN_OK;
 }
 
-// z = M^{-1} v in the preconditioner's precision (v, z FP64).
-dgtn_status precondition(dgtn_ctx* c, int prec, const VOpts& o, const double* v, double* z, hipStream_t s) {
+// The FP32 preconditioner's input is the FP64 vector times scale32, a power of
+// two, and its output is divided by it: exact in FP64, and for a vector of RMS
+// entry about 1 it keeps the FP32 values in the normal range.  (An adjoint load
+// of S_x, 4 kB T phi / (pi f F0^2) ~ 1e-27 times the layer energy operators,
+// otherwise puts the small residual entries below FP32's 1.2e-38, where they
+// lose their digits: the FP32-preconditioned solve of the forty-layer mirror's
+// adjoint stalled near 2e-6.)  Where all values stay normal, the roundings are
+// those of the unscaled vector: the solve is unchanged bit for bit.
+double fp32_scale(double norm, size_t n) {
+    if (!(norm > 0) || !std::isfinite(norm) || n == 0) return 1.0;
+    int e = 0;
+    std::frexp(norm / std::sqrt((double)n), &e);
+    return std::ldexp(1.0, std::max(-900, std::min(900, -e)));
+}
+
+// z = M^{-1} v in the preconditioner's precision (v, z FP64); scale32 as above.
+dgtn_status precondition(dgtn_ctx* c, int prec, const VOpts& o, const double* v, double* z, hipStream_t s,
+                         double scale32 = 1.0) {
     SolverState& S = *c->solver;
     const size_t n = ndof(c->levels[0]);
     if (o.identity) {
@@ -1192,10 +1208,10 @@ dgtn_status precondition(dgtn_ctx* c, int prec, const VOpts& o, const double* v,
         return DGTN_OK;
     }
     if (prec == 32) {
-        SHIP(vec_cast<double, float>(v, at<float>(c, S.mg[0].off_b[1]), n, 1.0, s));
+        SHIP(vec_cast<double, float>(v, at<float>(c, S.mg[0].off_b[1]), n, scale32, s));
         dgtn_status st = vcycle_launch(c, 32, o, s);
         if (st != DGTN_OK) return st;
-        SHIP(vec_cast<float, double>(at<float>(c, S.mg[0].off_x[1]), z, n, 1.0, s));
+        SHIP(vec_cast<float, double>(at<float>(c, S.mg[0].off_x[1]), z, n, 1.0 / scale32, s));
     } else {
         SHIP(vec_cast<double, double>(v, at<double>(c, S.mg[0].off_b[0]), n, 1.0, s));
         dgtn_status st = vcycle_launch(c, 64, o, s);
@@ -1335,7 +1351,15 @@ extern "C" dgtn_status dgtn_precondition(dgtn_ctx* c, const dgtn_solve_opts* opt
         set_error("precond_precision must be 64 or 32"); return DGTN_EINVAL;
     }
     const VOpts vo{opts->smooth_steps, opts->smooth_damping, opts->mg_levels == 0, opts->smoother};
-    return precondition(c, opts->precond_precision, vo, v, z, s);
+    double scale32 = 1.0;
+    if (opts->precond_precision == 32 && !vo.identity) {
+        std::vector<double> d;
+        const size_t n = ndof(c->levels[0]);
+        const dgtn_status st = dots(c, nullptr, 0, v, n, d, s);
+        if (st != DGTN_OK) return st;
+        scale32 = fp32_scale(std::sqrt(d[0]), n);
+    }
+    return precondition(c, opts->precond_precision, vo, v, z, s, scale32);
 }
 
 extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, const double* b, double* u,
@@ -1380,6 +1404,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
     if ((st = dots(c, nullptr, 0, b, n, d, s)) != DGTN_OK) return st;
     const double bnorm = std::sqrt(d[0]);
     if (!std::isfinite(bnorm)) { set_error("non-finite right-hand side"); return DGTN_ENAN; }
+    const double s32 = fp32_scale(bnorm, n);  // FP32 preconditioner input scaling
     // b - A u into `out`, in FP64 or (residual_precision 128) double-double
     const bool dd_resid = opts->residual_precision == 128;
     auto residual_into = [&](double* out) -> dgtn_status {
@@ -1428,7 +1453,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         const double* dy[4];
         // (re)start from the residual in pr: z = M r, p = z, slot(par)[0] = r.z
         auto start = [&]() -> dgtn_status {
-            dgtn_status e = precondition(c, opts->precond_precision, vo, pr, zn, s);
+            dgtn_status e = precondition(c, opts->precond_precision, vo, pr, zn, s, s32);
             if (e != DGTN_OK) return e;
             SHIP(vec_cast<double, double>(zn, pp, n, 1.0, s));
             dx[0] = pr; dy[0] = zn;
@@ -1453,7 +1478,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
             SHIP(vec_dotpairs(1, dx, dy, n, at<double>(c, S.off_partial), S.nblk, sc, s));
             // FP32 V-cycle: the update writes its input and the dot products widen its
             // output (the same roundings as precondition's two casts, without their passes)
-            SHIP(fcg_update(u, pr, pp, q, cur, sc, b32, n, s));
+            SHIP(fcg_update(u, pr, pp, q, cur, sc, b32, s32, n, s));
             const int it = iters++;
             const bool replace = iters % refresh == 0;
             if (replace) {  // residual replacement
@@ -1461,12 +1486,12 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
                 ++restarts;
             }
             if (b32) {
-                if (replace) SHIP(vec_cast<double, float>(pr, b32, n, 1.0, s));
+                if (replace) SHIP(vec_cast<double, float>(pr, b32, n, s32, s));
                 if ((st = vcycle_launch(c, 32, vo, s)) != DGTN_OK) return st;
-                SHIP(vec_dot3_widen(pr, at<float>(c, S.mg[0].off_x[1]), zn, zo, n, at<double>(c, S.off_partial),
+                SHIP(vec_dot3_widen(pr, at<float>(c, S.mg[0].off_x[1]), zn, zo, 1.0 / s32, n, at<double>(c, S.off_partial),
                                     S.nblk, nxt, s));
             } else {
-                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s)) != DGTN_OK) return st;
+                if ((st = precondition(c, opts->precond_precision, vo, pr, zn, s, s32)) != DGTN_OK) return st;
                 dx[0] = pr; dy[0] = zn;
                 dx[1] = pr; dy[1] = zo;
                 dx[2] = pr; dy[2] = pr;
@@ -1539,7 +1564,7 @@ extern "C" dgtn_status dgtn_solve(dgtn_ctx* c, const dgtn_solve_opts* opts, cons
         for (; j < m && iters < opts->max_iter; ++j) {
             double* Vj = V + (size_t)j * n;
             double* Zj = Z + (size_t)j * n;
-            if ((st = precondition(c, opts->precond_precision, vo, Vj, Zj, s)) != DGTN_OK) return st;
+            if ((st = precondition(c, opts->precond_precision, vo, Vj, Zj, s, s32)) != DGTN_OK) return st;
             if ((st = level_apply<double>(c, 0, Zj, w, yr, s)) != DGTN_OK) return st;
             // classical Gram-Schmidt, repeated when the first pass cancels strongly
             if ((st = dots(c, V, j + 1, w, n, d, s)) != DGTN_OK) return st;

@@ -87,11 +87,10 @@ Engine = Callable[[dict, List[Tuple[str, int]], np.ndarray, Callable], Tuple[np.
 def device_engine(opts=None, max_rel_res: Optional[float] = None) -> Engine:
     """Evaluates (U, J, dJ/dtheta) with the library: forward solve, layer
     energies, adjoint solve and dgtn_grad on the current device.  A solve that
-    stagnates above its rtol (at the FP64 residual floor of thin layers, or at
-    the limit of an FP32 preconditioner on an adjoint load concentrated on them)
-    raises, unless max_rel_res is given and the relative residual it reached is
-    within it: the energies and the gradient then carry an error of first order
-    in that residual."""
+    stagnates above its rtol (at the FP64 residual floor of thin layers) raises,
+    unless max_rel_res is given and the relative residual it reached is within
+    it: the energies and the gradient then carry an error of first order in that
+    residual."""
 
     def solve(P, o, b=None):
         x, st = P.solve(b=b, opts=o, raise_on_noconv=max_rel_res is None)

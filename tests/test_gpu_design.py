@@ -68,7 +68,7 @@ def test_forty_layer_mirror_thicknesses():
     r = design.optimize(spec, [("thickness", k) for k in range(n)], design.NoiseObjective(phi, 300.0, 100.0),
                         constraints=[design.fixed_sum(range(n), float(d0.sum()))],
                         bounds=[(0.5 * d, 1.5 * d) for d in d0], tol=1e-9, maxiter=30,
-                        engine=design.device_engine(dgtn.default_opts(64, rtol=5e-8, max_iter=2000),
+                        engine=design.device_engine(dgtn.default_opts(32, rtol=5e-8, max_iter=2000),
                                                     max_rel_res=1e-6))
     assert r.success, r.message
     np.testing.assert_allclose(r.x[~is_a], 1.5 * d0[~is_a], rtol=1e-9)

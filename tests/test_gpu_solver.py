@@ -402,3 +402,25 @@ def test_thin_coating_solve_satisfies_the_oracle_system():
     r32 = np.linalg.norm(b - dg.apply(O, u32.cpu().numpy())) / bn
     print(f"oracle residuals: FP64-preconditioned {r64:.2e}, FP32-preconditioned {r32:.2e}", flush=True)
     assert r64 < 2e-9 and r32 < 2e-7
+
+
+@pytest.mark.parametrize("krylov", ["fcg", "fgmres"])
+def test_fp32_preconditioner_input_is_scaled_into_range(krylov):
+    """The FP32 V-cycle sees the residual times a power of two chosen from ||b||,
+    and its output is divided by it.  So a load scaled by 2^-100 (entries near
+    1e-30, whose small residual entries would fall below FP32's normal range)
+    gives the solution scaled by exactly 2^-100, in the same iterations: before
+    the scaling, such loads (the adjoint load of S_x is ~1e-27 times the layer
+    energy operators) stalled the FP32-preconditioned solve near 2e-6."""
+    spec = W.config4()
+    spec["p"] = 3
+    P = dgtn.Problem(spec)
+    o = (dgtn.default_opts(32, rtol=1e-9, max_iter=4000) if krylov == "fcg" else
+         dgtn.default_opts(32, krylov=0, restart=60, rtol=1e-7, max_iter=20000))
+    b = P.rhs()
+    u1, st1 = P.solve(b, opts=o)
+    tiny = 2.0 ** -100
+    u2, st2 = P.solve(b * tiny, opts=o)
+    assert st2.iters == st1.iters, (st1.iters, st2.iters)
+    assert torch.equal(u2, u1 * tiny)
+    P.close()
