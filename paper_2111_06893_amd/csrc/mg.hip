@@ -537,6 +537,145 @@ __global__ __launch_bounds__(256, gemm_waves<R>()) void k_col_gemm_mfma(int n, i
         }
 }
 
+// The FP32 z-products on split bf16: each operand x is held as hi + lo, two
+// bf16 numbers (hi = bf16(x), lo = bf16(x - hi), about 16 significant bits
+// together, and bf16 has FP32's exponent range), and a block product is
+// lo*hi + hi*lo + hi*hi on 16 x 16 x 16 bf16 MFMA with FP32 accumulation (the
+// lo*lo term, 2^-16 smaller, is left out).  Three bf16 instructions take about a
+// fifth of the matrix-core time of the FP32 instructions for the same K, and
+// the smoother is a preconditioner: solves with operands rounded to this
+// precision took the same iterations and gave the same energies as FP32 (forty
+// layers and thin coating, every tolerance).  64 x 64 output tiles, K chunks of
+// 32 split once when staged; in LDS each row keeps its 32 k (72-byte stride), so
+// a lane's four k of a fragment are one 8-byte read.  The eigenvalue division
+// and the clamped, deferred-zeroing fetch are those of k_col_gemm_mfma.
+constexpr int kBfRow = 36;  // bf16 per staged row: 32 k and 4 of padding
+
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    hi = __builtin_bit_cast(unsigned short, h);
+    lo = __builtin_bit_cast(unsigned short, l);
+}
+
+template <int W, int div>
+__global__ __launch_bounds__(256) void k_col_gemm_bf3(int n, int ncol, const float* __restrict__ A,
+                                                      const float* __restrict__ in, float* __restrict__ out,
+                                                      const float* __restrict__ lz, const float* __restrict__ lam,
+                                                      const float* __restrict__ rat) {
+    typedef short s4_t __attribute__((ext_vector_type(4)));
+    constexpr int TM = 64, TN = 64, PA = kGK * TM / 512, PB = kGK * TN / 512;
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[TM * kBfRow], Al[TM * kBfRow], Bh[TN * kBfRow],
+        Bl[TN * kBfRow];
+    const int c = blockIdx.z, row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
+    const int g4 = 4 * (lane / 16), l16 = lane % 16;
+    const float* Ac = A + (size_t)c * n * n;
+    const float* Bc = in + (size_t)c * n * ncol;
+    float ra[PA][2], rb[PB][2];
+    bool va[PA][2], vb[PB][2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < PA; ++t) {
+            const int q = tid + 256 * t, rg = row0 + q % TM, kp = k0 + 2 * (q / TM);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                ra[t][h] = Ac[(size_t)min(kp + h, n - 1) * n + min(rg, n - 1)];
+                va[t][h] = kp + h < n && rg < n;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+            const int q = tid + 256 * t, cg = col0 + q % TN, kp = k0 + 2 * (q / TN);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                rb[t][h] = Bc[(size_t)min(kp + h, n - 1) * ncol + min(cg, ncol - 1)];
+                vb[t][h] = kp + h < n && cg < ncol;
+            }
+        }
+    };
+    auto stage = [](float x0, float x1, unsigned short* hi, unsigned short* lo, int o) {
+        unsigned short h0, l0, h1, l1;
+        split_bf16(x0, h0, l0);
+        split_bf16(x1, h1, l1);
+        *reinterpret_cast<unsigned*>(&hi[o]) = h0 | ((unsigned)h1 << 16);
+        *reinterpret_cast<unsigned*>(&lo[o]) = l0 | ((unsigned)l1 << 16);
+    };
+    f4_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0, 0, 0, 0};
+    fetch(0);
+    float lxy[2];
+    if constexpr (div) {
+        constexpr int W2 = W * W;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int cg = min(col0 + wc + 16 * b + l16, ncol - 1);
+            const int colm = cg / W2, ab = cg % W2, bb = ab / W, aa = ab % W;
+            lxy[b] = rat[(size_t)colm * 6 + c * 2 + 0] * lam[((size_t)colm * 2 + 0) * W + aa] +
+                     rat[(size_t)colm * 6 + c * 2 + 1] * lam[((size_t)colm * 2 + 1) * W + bb];
+        }
+    }
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+#pragma unroll
+        for (int t = 0; t < PA; ++t) {
+            const int q = tid + 256 * t;
+            stage(va[t][0] ? ra[t][0] : 0.f, va[t][1] ? ra[t][1] : 0.f, Ah, Al, (q % TM) * kBfRow + 2 * (q / TM));
+        }
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+            const int q = tid + 256 * t;
+            stage(vb[t][0] ? rb[t][0] : 0.f, vb[t][1] ? rb[t][1] : 0.f, Bh, Bl, (q % TN) * kBfRow + 2 * (q / TN));
+        }
+        __syncthreads();
+        if (k0 + kGK < n) fetch(k0 + kGK);
+#pragma unroll
+        for (int ks = 0; ks < kGK; ks += 16) {
+            s4_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int o = (wr + 16 * a + l16) * kBfRow + ks + g4;
+                ah[a] = *reinterpret_cast<const s4_t*>(&Ah[o]);
+                al[a] = *reinterpret_cast<const s4_t*>(&Al[o]);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int o = (wc + 16 * b + l16) * kBfRow + ks + g4;
+                bh[b] = *reinterpret_cast<const s4_t*>(&Bh[o]);
+                bl[b] = *reinterpret_cast<const s4_t*>(&Bl[o]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    float* Oc = out + (size_t)c * n * ncol;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int cg = col0 + wc + 16 * b + l16;
+            if (cg >= ncol) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rg = row0 + wr + 16 * a + g4 + q;  // the 16 x 16 output layout of the FP32 instruction
+                if (rg >= n) continue;
+                float v = acc[a][b][q];
+                if constexpr (div) v /= lz[(size_t)c * n + rg] + lxy[b];
+                Oc[(size_t)rg * ncol + cg] = v;
+            }
+        }
+}
+
 // Fine += P coarse over the same elements, P = I (x) I (x) I with I [Nf][Nc].
 // NF, NC: the sizes as compile-time constants (the pairs p -> max(1, p / 2)
 // produces), or 0 to take them from the arguments.
@@ -1122,13 +1261,49 @@ hipError_t col_gemm_pair_t(int W, int n, int ncol, const R* V, R* T, R* Y, const
     return hipGetLastError();
 }
 
+// FP32 on split bf16 (k_col_gemm_bf3), 64 x 64 tiles
+inline hipError_t col_gemm_pair_bf3(int W, int n, int ncol, const float* V, float* T, float* Y, const float* lz,
+                                    const float* lam, const float* rat, hipStream_t s) {
+    const dim3 grid((ncol + 63) / 64, (n + 63) / 64, 3);
+    hipError_t err = hipErrorInvalidValue;
+    auto fwd = [&](auto w) {
+        constexpr int WW = decltype(w)::value;
+        hipLaunchKernelGGL((k_col_gemm_bf3<WW, 1>), grid, dim3(256), 0, s, n, ncol, V, T, Y, lz, lam, rat);
+        return hipGetLastError();
+    };
+    switch (W) {
+        case 2: err = fwd(std::integral_constant<int, 2>{}); break;
+        case 3: err = fwd(std::integral_constant<int, 3>{}); break;
+        case 4: err = fwd(std::integral_constant<int, 4>{}); break;
+        case 5: err = fwd(std::integral_constant<int, 5>{}); break;
+        case 6: err = fwd(std::integral_constant<int, 6>{}); break;
+        case 7: err = fwd(std::integral_constant<int, 7>{}); break;
+        case 8: err = fwd(std::integral_constant<int, 8>{}); break;
+        case 9: err = fwd(std::integral_constant<int, 9>{}); break;
+        case 10: err = fwd(std::integral_constant<int, 10>{}); break;
+        case 11: err = fwd(std::integral_constant<int, 11>{}); break;
+        case 12: err = fwd(std::integral_constant<int, 12>{}); break;
+        case 13: err = fwd(std::integral_constant<int, 13>{}); break;
+        case 14: err = fwd(std::integral_constant<int, 14>{}); break;
+        default: break;
+    }
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_col_gemm_bf3<0, 0>), grid, dim3(256), 0, s, n, ncol, V + (size_t)3 * n * n, Y, T, lz, lam,
+                       rat);
+    return hipGetLastError();
+}
+
+// Small grids (fewer 64 x 64 tiles than compute units): 32 x 32 tiles in the
+// working precision.  Otherwise FP32 runs on split bf16 (forty-layer finest
+// level 163 -> 120 us per product in a probe) and FP64 on 64 x 64 FP64 tiles.
 template <typename R>
 hipError_t col_gemm_pair(int W, int n, int ncol, const R* V, R* T, R* Y, const R* lz, const R* lam, const R* rat,
                          hipStream_t s) {
     constexpr long kComputeUnits = 256;
     const long tiles64 = 3L * ((ncol + 63) / 64) * ((n + 63) / 64);
-    return tiles64 < kComputeUnits ? col_gemm_pair_t<R, 32>(W, n, ncol, V, T, Y, lz, lam, rat, s)
-                                   : col_gemm_pair_t<R, 64>(W, n, ncol, V, T, Y, lz, lam, rat, s);
+    if (tiles64 < kComputeUnits) return col_gemm_pair_t<R, 32>(W, n, ncol, V, T, Y, lz, lam, rat, s);
+    if constexpr (sizeof(R) == 4) return col_gemm_pair_bf3(W, n, ncol, V, T, Y, lz, lam, rat, s);
+    return col_gemm_pair_t<R, 64>(W, n, ncol, V, T, Y, lz, lam, rat, s);
 }
 
 // (Nf, Nc) pairs of the p-coarsening as compile-time constants; other pairs run
