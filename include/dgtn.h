@@ -234,7 +234,10 @@ dgtn_status dgtn_residual(dgtn_ctx* ctx, const double* b, const double* u, doubl
  * smoother setting) as a HIP graph on a stream the library owns and replayed
  * on `stream`; with the environment variable DGTN_NO_GRAPHS set when the
  * solver state is created, or if recording fails, it is launched kernel by
- * kernel instead (same kernels, same results). */
+ * kernel instead (same kernels, same results).  In FP32 the V-cycle's input is
+ * v times a power of two chosen from ||v|| (here; from ||b|| in dgtn_solve) and
+ * its output is divided by it, so that small vectors keep FP32's normal range;
+ * computing ||v|| synchronises the stream. */
 dgtn_status dgtn_precondition(dgtn_ctx* ctx, const dgtn_solve_opts* opts, const double* v, double* z,
                               hipStream_t stream);
 
