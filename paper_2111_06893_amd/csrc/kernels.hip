@@ -33,7 +33,7 @@ __global__ __launch_bounds__(op_threads<N>()) void k_traction(LevelView<R> L, co
     const int tid = threadIdx.x;
     const int col = e % L.n_cols, iz = e / L.n_cols;
     const R* ue = u + (size_t)e * 3 * N3;
-    const LineTasks<N, NT> tasks = line_tasks<N, NT>(tid);
+    const LineTasks<N, NT> tasks = line_tasks<N, NT, true>(tid);  // face nodes only
     // waves 1.. stage u while wave 0 reads the element's material (two dependent
     // table reads), so that the two latencies overlap instead of adding up
     if (tid >= 64) {
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(op_threads<N>()) void k_traction(LevelView<R> L, co
     if (act) face_node<N>(f, fi, i, j, k);
     NodeGeo<R> g = act ? node_geo<N>(L, col, iz, i, j) : NodeGeo<R>{1, 0, 0, 1, 1, 1};
     __syncthreads();
-    ref_derivatives<N, R, NT>(L, su, sG, tid, tasks);
+    ref_derivatives<N, R, NT, true>(L, su, sG, tid, tasks);
     __syncthreads();
     if (!act) return;
     R G[3][3], S[6], T[6], t[3];
